@@ -1,0 +1,212 @@
+/*
+ * fskmc.h -- C ABI of libfskmc, a fractional-step parallel lattice kinetic
+ * Monte Carlo library for AMD Instinct MI355X (gfx950).
+ *
+ * The method (Arampatzis, Katsoulakis, Plechac, Taufer, Xu, "Hierarchical
+ * fractional-step approximations and parallel kinetic Monte Carlo
+ * algorithms"): the generator of a lattice Markov jump process (Sec. 2,
+ * eq. generator) is split over a colouring of the lattice into blocks
+ * (Sec. 2.1, eqs. decomposition, sublatt, opdecomp).  A Trotter product
+ * (Sec. 2.2, eq. lie; Sec. 3, eq. strang; Sec. 3.1, eq. SLPCS) turns the
+ * evolution into a sequence of windows; in each window every block of the
+ * active colour runs its own serial SSA kernel independently (eq. exact)
+ * while all other sites are frozen (the three-stage step of Sec. 2.2).
+ *
+ * Conventions for every call:
+ *  - Every function returns an int status: FSKMC_OK (0) or a negative code
+ *    below.  The human-readable reason of the last failure on the calling
+ *    thread is returned by fskmc_last_error().  Nothing throws across the ABI.
+ *  - Handles are opaque; every create has a matching destroy.  Memory the
+ *    library allocates it also frees.  Host buffers passed in are owned by the
+ *    caller and copied before the call returns.
+ *  - Sites are bytes, indexed y*Lx + x on a periodic Lx x Ly lattice (Ly = 1
+ *    in 1D).  States: spin-flip {0,1}; reaction model {0 empty, 1 A, 2 B}.
+ *  - Work is enqueued asynchronously on the context's HIP stream; calls that
+ *    return host data synchronise that stream first.
+ *  - Results are a pure function of (model, lattice, decomposition, schedule,
+ *    key): the same inputs give the same bits whether a simulation is advanced
+ *    alone or inside a batch.
+ */
+#ifndef FSKMC_H
+#define FSKMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FSKMC_OK = 0,
+    FSKMC_EINVAL = -1,  /* bad argument, shape or parameter                     */
+    FSKMC_ENOMEM = -2,  /* host or device allocation failed / over budget       */
+    FSKMC_EDEVICE = -3, /* a HIP runtime call failed                             */
+    FSKMC_EDECOMP = -4, /* colour map does not tile or blocks of a colour interact */
+    FSKMC_EBUSY = -5,   /* object still in use (e.g. a sim inside a running batch) */
+    FSKMC_ESTATE = -6   /* call not valid in the current state (e.g. past T)     */
+};
+
+typedef struct fskmc_ctx fskmc_ctx; /* one GPU + one HIP stream            */
+typedef struct fskmc_sim fskmc_sim; /* one lattice replica / job            */
+
+/* Models (Sec. 2 examples; Sec. 7 eq. Arrhenius; Sec. 7.1 Table COrates). */
+typedef enum {
+    FSKMC_MODEL_FLIP = 1, /* Arrhenius adsorption/desorption spin flip, states {0,1} */
+    FSKMC_MODEL_ZGB = 2   /* A adsorption, B2 dissociative adsorption, A+B reaction,
+                             A hopping; states {0,1=A,2=B}; pair events              */
+} fskmc_model;
+
+/* Processor communication schedules (Sec. 3, eqs. PCSl, PCSs, SLPCS). */
+typedef enum {
+    FSKMC_LIE = 0,    /* per step: colours 0..K-1, each for dt                      */
+    FSKMC_STRANG = 1, /* per step: 0..K-2 for dt/2, K-1 for dt, K-2..0 for dt/2     */
+    FSKMC_RANDOM = 2  /* per step: K windows of dt, colour uniform from Philox (w,0,0,3) */
+} fskmc_split;
+
+/* Lattice Lambda_N (Sec. 2): dim 1 (Ly must be 1) or 2, periodic. */
+typedef struct {
+    int dim;
+    int Lx, Ly;
+} fskmc_lattice;
+
+/* Spin-flip rates (Sec. 4.1 eq. adsdesrate with eq. potential; Sec. 7 eq.
+ * Arrhenius): c(x) = k_a if sigma(x) = 0, and
+ * k_d * exp(-(beta * (J * n + h))) if sigma(x) = 1, n = #occupied neighbours. */
+typedef struct {
+    double k_a, k_d, J, h, beta;
+} fskmc_flip_params;
+
+/* Reaction-model rates (Sec. 7.1, Table COrates), per site x and direction d:
+ * A adsorption y; B2 dissociative adsorption on (x, x+e_d) (1-y)/4;
+ * A+B -> 0+0 with x+e_d at k_r/4; A hop to an empty x+e_d at D/4. */
+typedef struct {
+    double y, k_r, D;
+} fskmc_zgb_params;
+
+/* Decomposition (Sec. 2.1): blocks of bx x by sites tile the lattice; block
+ * m = bj*(Lx/bx) + bi.  colour_map (length #blocks, values in [0, n_colours))
+ * may be NULL for the built-in maps: 2 colours (bi+bj)%2, 4 colours
+ * (bi%2) + 2*(bj%2).  The GPU kernels need bx*by = 64*P with P in {1,4,16}
+ * and either square blocks (8x8, 16x16, 32x32) or 1D rows (64P x 1). */
+typedef struct {
+    int bx, by, n_colours;
+    const int* colour_map;
+} fskmc_decomp;
+
+/* Schedule: window length dt and final time T (Sec. 2.2, T = n dt; T/dt must
+ * be an integer to 1e-9 relative, else FSKMC_EINVAL). */
+typedef struct {
+    double dt, T;
+    int split; /* fskmc_split */
+} fskmc_schedule;
+
+/* Philox4x32-10 key (Salmon et al., SC'11).  Draw e of block m in window w
+ * uses counter (e, m, w, 0); the Bernoulli initial state uses (site, 0, 0, 1). */
+typedef struct {
+    uint32_t seed, replica;
+} fskmc_key;
+
+/* Integer observables at a window boundary (Sec. 7: coverage and two-point
+ * correlations are derived from these counts on the host). */
+typedef struct {
+    int64_t n_sites;
+    int64_t count[3];       /* sites per state                              */
+    int64_t bonds_equal[3]; /* nearest-neighbour bonds (+x, +y) with both ends in state k */
+    int64_t bonds_ab;       /* A-B bonds (reaction model)                    */
+    uint64_t window;        /* windows completed                             */
+    uint64_t steps;         /* complete fractional steps (t = steps * dt)    */
+    uint64_t events;        /* accepted events since the last init/set_state */
+    uint64_t block_windows; /* block-windows run since the last init/set_state */
+    uint64_t writes;        /* block-windows with at least one event (written back) */
+    double t;               /* physical time at the last complete step       */
+} fskmc_obs;
+
+/* Create a context on HIP device `device`.  hip_stream: an existing
+ * hipStream_t (e.g. torch.cuda.current_stream().cuda_stream) used for all
+ * work, or NULL for a library-owned stream.  out: receives the handle. */
+int fskmc_ctx_create(int device, void* hip_stream, fskmc_ctx** out);
+int fskmc_ctx_destroy(fskmc_ctx* ctx);
+
+/* Message of the last failed call on this thread ("" if none).  The pointer
+ * stays valid until the next failing call on the same thread. */
+const char* fskmc_last_error(void);
+
+/* Create one simulation: builds the FP64 rate table on the host, checks the
+ * decomposition (FSKMC_EDECOMP if two blocks of one colour can interact:
+ * spin flip writes C_m and reads C_m plus its neighbours; pair models read
+ * and write C_m plus its neighbours), builds the window schedule and
+ * allocates the device state.  params points at fskmc_flip_params or
+ * fskmc_zgb_params.  The lattice starts empty (all zeros). */
+int fskmc_sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const void* params,
+                     const fskmc_decomp* decomp, const fskmc_schedule* schedule, fskmc_key key,
+                     fskmc_sim** out);
+int fskmc_sim_destroy(fskmc_sim* sim);
+
+/* Use caller-owned device memory (e.g. a torch uint8 tensor of Lx*Ly bytes)
+ * as the lattice instead of the library's buffer.  The current lattice is
+ * copied into it.  The buffer must outlive the sim. */
+int fskmc_sim_attach_device_lattice(fskmc_sim* sim, void* dev_ptr, size_t bytes);
+
+/* Initial state: kind 0 = empty, 1 = Bernoulli(p) per site from Philox
+ * counter (site, 0, 0, 1).  Resets the window index and event counters. */
+int fskmc_sim_init(fskmc_sim* sim, int kind, double p);
+
+/* Copy a host lattice of n = Lx*Ly bytes in / out (get synchronises). */
+int fskmc_sim_set_lattice(fskmc_sim* sim, const uint8_t* host, size_t n);
+int fskmc_sim_get_lattice(fskmc_sim* sim, uint8_t* host, size_t n);
+
+/* Enqueue the next n_windows windows of the schedule (one kernel launch per
+ * window).  FSKMC_ESTATE if that would pass the final time T. */
+int fskmc_sim_advance(fskmc_sim* sim, uint64_t n_windows);
+/* Enqueue all remaining windows. */
+int fskmc_sim_run_to_end(fskmc_sim* sim);
+/* Number of windows in the schedule and the index of the next one. */
+int fskmc_sim_windows(const fskmc_sim* sim, uint64_t* total, uint64_t* next);
+
+/* Integer observables of the current lattice (synchronises). */
+int fskmc_sim_observe(fskmc_sim* sim, fskmc_obs* out);
+
+/* Accepted events per block in the last window each block ran (the workload
+ * W of Sec. 6, eq. wload); n_blocks = (Lx/bx)*(Ly/by).  Synchronises. */
+int fskmc_sim_block_events(fskmc_sim* sim, uint32_t* out, size_t n_blocks);
+
+/* The host-built FP64 rate table.  Spin flip: 2*(z+1) entries [s*(z+1)+n];
+ * reaction model: 243*14 entries [pattern*14 + c], 13 channels then the site
+ * total, pattern = s + 3 nE + 9 nW + 27 nN + 81 nS.  n = capacity. */
+int fskmc_sim_rate_table(const fskmc_sim* sim, double* out, size_t n);
+
+/* Checkpoint / resume: the state is (lattice, next window index) because the
+ * generator is counter-based.  get synchronises. */
+int fskmc_sim_get_state(fskmc_sim* sim, uint64_t* window, uint8_t* host, size_t n);
+int fskmc_sim_set_state(fskmc_sim* sim, uint64_t window, const uint8_t* host, size_t n);
+
+/* Device bytes one simulation of this shape needs (admission control). */
+size_t fskmc_sim_footprint(const fskmc_lattice* lattice, int model, const fskmc_decomp* decomp,
+                           const fskmc_schedule* schedule);
+
+/* Advance n simulations (same context) by up to `windows` windows each in
+ * one launch per window: every launch runs the current window of every sim
+ * that still has windows left, all blocks of all sims packed into one grid.
+ * Each sim's result is bit-identical to advancing it alone. */
+int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t windows);
+
+/* Wait for all work enqueued on the context's stream. */
+int fskmc_sync(fskmc_ctx* ctx);
+
+/* Knobs that never change results: waves (blocks) per workgroup for the sweep
+ * kernels (1, 2, 4 or 8). */
+int fskmc_ctx_set_waves_per_group(fskmc_ctx* ctx, int waves);
+
+/* Measurement aid.  With stride > 0, every stride-th sweep launch on this
+ * context is bracketed by two HIP timing events recorded on the context
+ * stream (stride 0 turns it off).  read returns the summed duration of the
+ * bracketed launches in milliseconds and their number since the previous
+ * read, then forgets them; it synchronises the stream. */
+int fskmc_ctx_set_kernel_timing(fskmc_ctx* ctx, int stride);
+int fskmc_ctx_read_kernel_timing(fskmc_ctx* ctx, double* total_ms, uint64_t* n_launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSKMC_H */

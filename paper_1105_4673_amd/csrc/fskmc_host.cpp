@@ -1,0 +1,984 @@
+// Host half of libfskmc: the C ABI declared in include/fskmc.h.
+//
+// Builds everything the kernels need before any launch -- the FP64 rate table
+// (exp evaluated here, never on the device), the block decomposition with its
+// independence check (Sec. 2.1), the window schedule (Sec. 2.2 eq. lie, Sec. 3
+// eqs. strang, PCSl, PCSs, SLPCS) -- then drives one kernel launch per window.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fskmc.h"
+#include "fskmc_internal.h"
+
+using namespace fskmc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(FSKMC_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+    } while (0)
+
+// Philox4x32-10 on the host, for the random schedule's colour draws only.
+void philox_host(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = (uint32_t)p1;
+        c[2] = n2;
+        c[3] = (uint32_t)p0;
+    }
+}
+
+}  // namespace
+
+struct fskmc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int wpg = 2;
+    unsigned long long* d_obs = nullptr;   // 9 counters
+    unsigned long long* h_obs = nullptr;   // pinned
+    // batched launches: packed job table and item -> job map (grown on demand)
+    JobDesc* d_jobs = nullptr;
+    size_t cap_jobs = 0;
+    uint32_t* d_items = nullptr;
+    size_t cap_items = 0;
+    uint8_t* h_stage = nullptr;            // pinned staging for the uploads
+    size_t cap_stage = 0;
+    hipEvent_t stage_free = nullptr;
+    // measurement aid: timing events around every timing_stride-th sweep launch
+    int timing_stride = 0;
+    uint64_t launch_counter = 0;
+    std::vector<hipEvent_t> ev_pool; // pairs (start, stop)
+    size_t ev_used = 0;              // pairs recorded since the last harvest
+    double timed_ms = 0.0;
+    uint64_t timed_n = 0;
+};
+
+struct fskmc_sim {
+    fskmc_ctx* ctx = nullptr;
+    int model = 0;
+    fskmc_lattice lat{};
+    double prm[5] = {0, 0, 0, 0, 0};
+    int bx = 0, by = 0, n_colours = 0, NBX = 0, NBY = 0, nb = 0, P = 0, shape = 0;
+    fskmc_schedule sched{};
+    fskmc_key key{};
+    std::vector<int> cmap;
+    std::vector<int32_t> blocks;      // grouped by colour
+    std::vector<int32_t> colour_off;  // n_colours + 1
+    int max_per_colour = 0;
+    std::vector<int8_t> win_colour;
+    std::vector<double> win_dur;
+    std::vector<uint8_t> step_end;
+    uint64_t n_windows = 0, window = 0;
+    uint64_t block_windows = 0; // since the last init / set_state
+    std::vector<double> table;
+    // device
+    uint8_t* d_lat = nullptr;
+    bool own_lat = true;
+    double* d_table = nullptr;
+    uint32_t* d_W = nullptr;
+    uint64_t* d_cum = nullptr;
+    uint32_t* d_cumw = nullptr;
+    int32_t* d_blocks = nullptr;
+    int32_t* d_coff = nullptr;
+    int8_t* d_wcol = nullptr;
+    double* d_wdur = nullptr;
+};
+
+namespace {
+
+int64_t n_sites(const fskmc_lattice& L) { return (int64_t)L.Lx * L.Ly; }
+
+int validate_lattice(const fskmc_lattice* L)
+{
+    if (!L)
+        return fail(FSKMC_EINVAL, "lattice is NULL");
+    if (L->dim != 1 && L->dim != 2)
+        return fail(FSKMC_EINVAL, "dim must be 1 or 2 (got %d)", L->dim);
+    if (L->Lx <= 0 || L->Ly <= 0)
+        return fail(FSKMC_EINVAL, "lattice sizes must be positive");
+    if (L->dim == 1 && L->Ly != 1)
+        return fail(FSKMC_EINVAL, "a 1D lattice has Ly == 1");
+    if ((int64_t)L->Lx * L->Ly > (int64_t)1 << 31)
+        return fail(FSKMC_EINVAL, "lattice larger than 2^31 sites");
+    return FSKMC_OK;
+}
+
+// GPU kernel variant for a block shape: P sites per lane, square or row.
+int kernel_shape(const fskmc_lattice& L, int model, int bx, int by, int* P, int* shape)
+{
+    if (L.dim == 2) {
+        if (bx != by || (bx != 8 && bx != 16 && bx != 32))
+            return fail(FSKMC_EINVAL, "2D blocks must be 8x8, 16x16 or 32x32 (got %dx%d)", bx, by);
+        *P = bx * by / 64;
+        *shape = SHAPE_SQ;
+    } else {
+        if (model != FSKMC_MODEL_FLIP)
+            return fail(FSKMC_EINVAL, "the reaction model is two-dimensional");
+        if (by != 1 || (bx != 64 && bx != 256 && bx != 1024))
+            return fail(FSKMC_EINVAL, "1D blocks must be 64, 256 or 1024 sites (got %dx%d)", bx, by);
+        *P = bx / 64;
+        *shape = SHAPE_ROW;
+    }
+    return FSKMC_OK;
+}
+
+// Neighbour of a site in direction d (0 +x, 1 -x, 2 +y, 3 -y), periodic.
+inline int64_t nbr(const fskmc_lattice& L, int64_t s, int d)
+{
+    int64_t x = s % L.Lx, y = s / L.Lx;
+    switch (d) {
+    case 0: x = (x + 1) % L.Lx; break;
+    case 1: x = (x + L.Lx - 1) % L.Lx; break;
+    case 2: y = (y + 1) % L.Ly; break;
+    default: y = (y + L.Ly - 1) % L.Ly; break;
+    }
+    return y * L.Lx + x;
+}
+
+// Independence of the blocks of each colour (Sec. 2.1, remark after eq.
+// gendecomp): no block may write a site that another block of the same colour
+// reads or writes.  Spin flip: W = C_m, R = C_m + N(C_m); pair events:
+// W = R = C_m + N(C_m).  One pass per colour with per-site owner marks.
+int check_decomposition(const fskmc_sim& S)
+{
+    const fskmc_lattice& L = S.lat;
+    const int64_t N = n_sites(L);
+    const int nd = L.dim == 1 ? 2 : 4;
+    const bool pair = S.model == FSKMC_MODEL_ZGB;
+    std::vector<int32_t> ownW((size_t)N), ownR((size_t)N);
+    for (int c = 0; c < S.n_colours; ++c) {
+        std::fill(ownW.begin(), ownW.end(), -1);
+        std::fill(ownR.begin(), ownR.end(), -1);
+        for (int k = S.colour_off[c]; k < S.colour_off[c + 1]; ++k) {
+            const int m = S.blocks[k];
+            const int64_t x0 = (int64_t)(m % S.NBX) * S.bx, y0 = (int64_t)(m / S.NBX) * S.by;
+            auto mark = [&](int64_t s, bool write) -> bool {
+                if (write) {
+                    if ((ownW[s] != -1 && ownW[s] != m) || (ownR[s] != -1 && ownR[s] != m))
+                        return false;
+                    ownW[s] = m;
+                }
+                if (ownW[s] != -1 && ownW[s] != m)
+                    return false;
+                if (ownR[s] == -1)
+                    ownR[s] = m;
+                else if (ownR[s] != m)
+                    ownR[s] = -2; // several readers: any other writer conflicts
+                return true;
+            };
+            for (int64_t y = y0; y < y0 + S.by; ++y)
+                for (int64_t x = x0; x < x0 + S.bx; ++x) {
+                    const int64_t s = y * L.Lx + x;
+                    if (!mark(s, true))
+                        return fail(FSKMC_EDECOMP, "blocks of colour %d interact at site %lld", c, (long long)s);
+                    for (int d = 0; d < nd; ++d)
+                        if (!mark(nbr(L, s, d), pair))
+                            return fail(FSKMC_EDECOMP, "blocks of colour %d interact near site %lld", c,
+                                        (long long)s);
+                }
+        }
+    }
+    return FSKMC_OK;
+}
+
+int build_schedule(fskmc_sim& S)
+{
+    const double dt = S.sched.dt, T = S.sched.T;
+    if (!(dt > 0.0) || !(T >= 0.0) || !std::isfinite(dt) || !std::isfinite(T))
+        return fail(FSKMC_EINVAL, "need dt > 0 and T >= 0");
+    const double nd = std::floor(T / dt + 0.5);
+    if (std::fabs(nd * dt - T) > 1e-9 * std::max(1.0, T))
+        return fail(FSKMC_EINVAL, "T / dt = %.17g is not an integer", T / dt);
+    if (S.sched.split != FSKMC_LIE && S.sched.split != FSKMC_STRANG && S.sched.split != FSKMC_RANDOM)
+        return fail(FSKMC_EINVAL, "unknown splitting %d", S.sched.split);
+    const int K = S.n_colours;
+    const int64_t steps = (int64_t)nd;
+    const int per = S.sched.split == FSKMC_STRANG ? 2 * K - 1 : K;
+    if (steps * per > ((int64_t)1 << 32) - 1)
+        return fail(FSKMC_EINVAL, "more than 2^32 windows");
+    const double half = 0.5 * dt;
+    S.win_colour.clear();
+    S.win_dur.clear();
+    S.step_end.clear();
+    S.win_colour.reserve((size_t)(steps * per));
+    S.win_dur.reserve((size_t)(steps * per));
+    uint32_t w = 0;
+    for (int64_t k = 0; k < steps; ++k) {
+        for (int i = 0; i < per; ++i, ++w) {
+            int c;
+            double d;
+            if (S.sched.split == FSKMC_LIE) {
+                c = i;
+                d = dt;
+            } else if (S.sched.split == FSKMC_STRANG) {
+                c = i < K ? i : 2 * (K - 1) - i;
+                d = c == K - 1 ? dt : half;
+            } else {
+                uint32_t ctr[4] = {w, 0u, 0u, 3u};
+                philox_host(ctr, S.key.seed, S.key.replica);
+                const uint64_t b = ((uint64_t)ctr[2] << 32) | ctr[3];
+                const double V = (double)(b >> 11) * 0x1p-53;
+                c = (int)(V * (double)K);
+                d = dt;
+            }
+            S.win_colour.push_back((int8_t)c);
+            S.win_dur.push_back(d);
+            S.step_end.push_back(i == per - 1 ? 1 : 0);
+        }
+    }
+    S.n_windows = S.win_colour.size();
+    return FSKMC_OK;
+}
+
+void build_table(fskmc_sim& S)
+{
+    if (S.model == FSKMC_MODEL_FLIP) {
+        const int z = S.lat.dim == 1 ? 2 : 4;
+        const double ka = S.prm[0], kd = S.prm[1], J = S.prm[2], h = S.prm[3], beta = S.prm[4];
+        S.table.assign(2 * (z + 1), 0.0);
+        for (int n = 0; n <= z; ++n) {
+            S.table[n] = ka;
+            S.table[(z + 1) + n] = kd * std::exp(-(beta * (J * (double)n + h)));
+        }
+    } else {
+        const double y = S.prm[0], kr = S.prm[1], D = S.prm[2];
+        S.table.assign(243 * 14, 0.0);
+        for (int pat = 0; pat < 243; ++pat) {
+            int r = pat;
+            const int s = r % 3;
+            r /= 3;
+            int nb[4];
+            for (int d = 0; d < 4; ++d) { // E, W, N, S
+                nb[d] = r % 3;
+                r /= 3;
+            }
+            double* ch = &S.table[(size_t)pat * 14];
+            if (s == 0)
+                ch[0] = y;
+            for (int d = 0; d < 4; ++d) {
+                if (s == 0 && nb[d] == 0)
+                    ch[1 + d] = (1.0 - y) / 4.0;
+                if ((s == 1 && nb[d] == 2) || (s == 2 && nb[d] == 1))
+                    ch[5 + d] = kr / 4.0;
+                if (s == 1 && nb[d] == 0)
+                    ch[9 + d] = D / 4.0;
+            }
+            double tot = 0.0;
+            for (int c = 0; c < 13; ++c)
+                tot = tot + ch[c];
+            ch[13] = tot;
+        }
+    }
+}
+
+template <class T>
+int dev_alloc(T** p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0)
+        count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(FSKMC_ENOMEM, "hipMalloc(%zu bytes) failed: %s", count * sizeof(T), hipGetErrorString(e));
+    }
+    return FSKMC_OK;
+}
+
+void free_sim_device(fskmc_sim* S)
+{
+    if (S->own_lat && S->d_lat)
+        (void)hipFree(S->d_lat);
+    (void)hipFree(S->d_table);
+    (void)hipFree(S->d_W);
+    (void)hipFree(S->d_cum);
+    (void)hipFree(S->d_cumw);
+    (void)hipFree(S->d_blocks);
+    (void)hipFree(S->d_coff);
+    (void)hipFree(S->d_wcol);
+    (void)hipFree(S->d_wdur);
+    S->d_lat = nullptr;
+}
+
+// Sum the recorded timing pairs (synchronises the stream).
+int harvest_timing(fskmc_ctx* c)
+{
+    if (c->ev_used == 0)
+        return FSKMC_OK;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < c->ev_used; ++i) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev_pool[2 * i], c->ev_pool[2 * i + 1]));
+        c->timed_ms += ms;
+        c->timed_n += 1;
+    }
+    c->ev_used = 0;
+    return FSKMC_OK;
+}
+
+// Start event of a timed launch, or -1 when this launch is not sampled.
+long timing_begin(fskmc_ctx* c)
+{
+    if (c->timing_stride <= 0 || (c->launch_counter++ % (uint64_t)c->timing_stride) != 0)
+        return -1;
+    if (c->ev_used * 2 == c->ev_pool.size()) {
+        if (c->ev_pool.size() >= 8192) {
+            if (harvest_timing(c))
+                return -1;
+        } else {
+            for (int k = 0; k < 256; ++k) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess)
+                    return -1;
+                c->ev_pool.push_back(e);
+            }
+        }
+    }
+    const size_t i = c->ev_used;
+    if (hipEventRecord(c->ev_pool[2 * i], c->stream) != hipSuccess)
+        return -1;
+    return (long)i;
+}
+
+void timing_end(fskmc_ctx* c, long i)
+{
+    if (i < 0)
+        return;
+    if (hipEventRecord(c->ev_pool[2 * (size_t)i + 1], c->stream) == hipSuccess)
+        c->ev_used++;
+}
+
+int reset_counters(fskmc_sim* S)
+{
+    hipStream_t st = S->ctx->stream;
+    S->block_windows = 0;
+    HIP_TRY(launch_fill_u32(S->d_W, S->nb, 0u, st));
+    HIP_TRY(launch_fill_u64(S->d_cum, S->nb, 0ull, st));
+    HIP_TRY(launch_fill_u32(S->d_cumw, S->nb, 0u, st));
+    return FSKMC_OK;
+}
+
+int enqueue_window(fskmc_sim* S, uint64_t w)
+{
+    const int c = S->win_colour[w];
+    SweepArgs a;
+    a.lat = S->d_lat;
+    a.table = S->d_table;
+    a.W_last = S->d_W;
+    a.cum_events = S->d_cum;
+    a.cum_writes = S->d_cumw;
+    a.blocks = S->d_blocks + S->colour_off[c];
+    a.n_blocks = S->colour_off[c + 1] - S->colour_off[c];
+    a.Lx = S->lat.Lx;
+    a.Ly = S->lat.Ly;
+    a.NBX = S->NBX;
+    a.k0 = S->key.seed;
+    a.k1 = S->key.replica;
+    a.w = (uint32_t)w;
+    a.dur = S->win_dur[w];
+    const long tk = timing_begin(S->ctx);
+    HIP_TRY(launch_sweep_single(S->model, S->P, S->shape, S->ctx->wpg, a, S->ctx->stream));
+    timing_end(S->ctx, tk);
+    S->block_windows += (uint64_t)a.n_blocks;
+    return FSKMC_OK;
+}
+
+size_t footprint_of(int64_t N, int model, int nb, uint64_t n_windows, int n_colours)
+{
+    const size_t tab = model == FSKMC_MODEL_FLIP ? 10 * 8 : 243 * 14 * 8;
+    return (size_t)N + tab + (size_t)nb * (4 + 8 + 4 + 4) + (size_t)(n_colours + 1) * 4 +
+           (size_t)n_windows * (1 + 8);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fskmc_last_error(void) { return g_err.c_str(); }
+
+int fskmc_ctx_create(int device, void* hip_stream, fskmc_ctx** out)
+{
+    if (!out)
+        return fail(FSKMC_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev)
+        return fail(FSKMC_EINVAL, "device %d out of range (%d devices)", device, ndev);
+    HIP_TRY(hipSetDevice(device));
+    fskmc_ctx* c = new fskmc_ctx();
+    c->device = device;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete c;
+            return fail(FSKMC_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+        }
+        c->own_stream = true;
+    }
+    if (hipMalloc((void**)&c->d_obs, 16 * sizeof(unsigned long long)) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_obs, 16 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->stage_free, hipEventDisableTiming) != hipSuccess) {
+        fskmc_ctx_destroy(c);
+        return fail(FSKMC_ENOMEM, "context allocation failed");
+    }
+    *out = c;
+    return FSKMC_OK;
+}
+
+int fskmc_ctx_destroy(fskmc_ctx* c)
+{
+    if (!c)
+        return FSKMC_OK;
+    (void)hipSetDevice(c->device);
+    if (c->stream)
+        (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->d_obs);
+    (void)hipHostFree(c->h_obs);
+    (void)hipFree(c->d_jobs);
+    (void)hipFree(c->d_items);
+    (void)hipHostFree(c->h_stage);
+    if (c->stage_free)
+        (void)hipEventDestroy(c->stage_free);
+    for (hipEvent_t e : c->ev_pool)
+        (void)hipEventDestroy(e);
+    if (c->own_stream && c->stream)
+        (void)hipStreamDestroy(c->stream);
+    delete c;
+    return FSKMC_OK;
+}
+
+int fskmc_ctx_set_kernel_timing(fskmc_ctx* c, int stride)
+{
+    if (!c)
+        return fail(FSKMC_EINVAL, "ctx is NULL");
+    if (stride < 0)
+        return fail(FSKMC_EINVAL, "stride must be >= 0");
+    c->timing_stride = stride;
+    c->launch_counter = 0;
+    return FSKMC_OK;
+}
+
+int fskmc_ctx_read_kernel_timing(fskmc_ctx* c, double* total_ms, uint64_t* n_launches)
+{
+    if (!c || !total_ms || !n_launches)
+        return fail(FSKMC_EINVAL, "NULL argument");
+    int rc = harvest_timing(c);
+    if (rc)
+        return rc;
+    *total_ms = c->timed_ms;
+    *n_launches = c->timed_n;
+    c->timed_ms = 0.0;
+    c->timed_n = 0;
+    return FSKMC_OK;
+}
+
+int fskmc_ctx_set_waves_per_group(fskmc_ctx* c, int waves)
+{
+    if (!c)
+        return fail(FSKMC_EINVAL, "ctx is NULL");
+    if (waves != 1 && waves != 2 && waves != 4 && waves != 8)
+        return fail(FSKMC_EINVAL, "waves per group must be 1, 2, 4 or 8");
+    c->wpg = waves;
+    return FSKMC_OK;
+}
+
+int fskmc_sync(fskmc_ctx* c)
+{
+    if (!c)
+        return fail(FSKMC_EINVAL, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return FSKMC_OK;
+}
+
+int fskmc_sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const void* params,
+                     const fskmc_decomp* decomp, const fskmc_schedule* schedule, fskmc_key key, fskmc_sim** out)
+{
+    if (!ctx || !out || !params || !decomp || !schedule)
+        return fail(FSKMC_EINVAL, "NULL argument");
+    *out = nullptr;
+    int rc = validate_lattice(lattice);
+    if (rc)
+        return rc;
+    if (model != FSKMC_MODEL_FLIP && model != FSKMC_MODEL_ZGB)
+        return fail(FSKMC_EINVAL, "unknown model %d", model);
+    fskmc_sim* S = new fskmc_sim();
+    S->ctx = ctx;
+    S->model = model;
+    S->lat = *lattice;
+    if (model == FSKMC_MODEL_FLIP) {
+        const fskmc_flip_params* p = (const fskmc_flip_params*)params;
+        double v[5] = {p->k_a, p->k_d, p->J, p->h, p->beta};
+        for (int i = 0; i < 5; ++i)
+            S->prm[i] = v[i];
+        if (!(p->k_a >= 0) || !(p->k_d >= 0) || !std::isfinite(p->J) || !std::isfinite(p->h) ||
+            !std::isfinite(p->beta) || !std::isfinite(p->k_a) || !std::isfinite(p->k_d)) {
+            delete S;
+            return fail(FSKMC_EINVAL, "spin-flip rates must be finite and k_a, k_d >= 0");
+        }
+    } else {
+        const fskmc_zgb_params* p = (const fskmc_zgb_params*)params;
+        S->prm[0] = p->y;
+        S->prm[1] = p->k_r;
+        S->prm[2] = p->D;
+        if (!(p->y >= 0 && p->y <= 1) || !(p->k_r >= 0) || !(p->D >= 0) || !std::isfinite(p->k_r) ||
+            !std::isfinite(p->D)) {
+            delete S;
+            return fail(FSKMC_EINVAL, "reaction model needs 0 <= y <= 1, k_r >= 0, D >= 0");
+        }
+    }
+    S->bx = decomp->bx;
+    S->by = decomp->by;
+    S->n_colours = decomp->n_colours;
+    S->sched = *schedule;
+    S->key = key;
+    if (S->bx <= 0 || S->by <= 0 || S->lat.Lx % S->bx || S->lat.Ly % S->by) {
+        delete S;
+        return fail(FSKMC_EINVAL, "blocks %dx%d do not tile %dx%d", decomp->bx, decomp->by, lattice->Lx, lattice->Ly);
+    }
+    if ((rc = kernel_shape(S->lat, model, S->bx, S->by, &S->P, &S->shape))) {
+        delete S;
+        return rc;
+    }
+    S->NBX = S->lat.Lx / S->bx;
+    S->NBY = S->lat.Ly / S->by;
+    S->nb = S->NBX * S->NBY;
+    if (S->n_colours < 1 || S->n_colours > 127) {
+        delete S;
+        return fail(FSKMC_EINVAL, "n_colours must be in [1,127]");
+    }
+    S->cmap.resize(S->nb);
+    for (int m = 0; m < S->nb; ++m) {
+        const int bi = m % S->NBX, bj = m / S->NBX;
+        int c;
+        if (decomp->colour_map) {
+            c = decomp->colour_map[m];
+        } else if (S->n_colours == 2) {
+            c = (bi + bj) % 2;
+        } else if (S->n_colours == 4) {
+            c = (bi % 2) + 2 * (bj % 2);
+        } else {
+            delete S;
+            return fail(FSKMC_EINVAL, "built-in colour maps have 2 or 4 colours");
+        }
+        if (c < 0 || c >= S->n_colours) {
+            delete S;
+            return fail(FSKMC_EINVAL, "colour_map[%d] = %d out of range", m, c);
+        }
+        S->cmap[m] = c;
+    }
+    S->colour_off.assign(S->n_colours + 1, 0);
+    for (int c = 0; c < S->n_colours; ++c) {
+        S->colour_off[c] = (int32_t)S->blocks.size();
+        for (int m = 0; m < S->nb; ++m)
+            if (S->cmap[m] == c)
+                S->blocks.push_back(m);
+        S->max_per_colour = std::max(S->max_per_colour, (int)S->blocks.size() - S->colour_off[c]);
+    }
+    S->colour_off[S->n_colours] = (int32_t)S->blocks.size();
+    if ((rc = check_decomposition(*S)) || (rc = build_schedule(*S))) {
+        delete S;
+        return rc;
+    }
+    build_table(*S);
+    // every rate finite and small enough that a block's total stays finite
+    // (an infinite total would give zero waiting times and a window that
+    // never ends)
+    for (double r : S->table) {
+        if (!std::isfinite(r) || r < 0.0 || !std::isfinite(r * 4096.0)) {
+            delete S;
+            return fail(FSKMC_EINVAL, "rate %g is not finite or too large", r);
+        }
+    }
+    (void)hipSetDevice(ctx->device);
+    const int64_t N = n_sites(S->lat);
+    if ((rc = dev_alloc(&S->d_lat, (size_t)N)) || (rc = dev_alloc(&S->d_table, S->table.size())) ||
+        (rc = dev_alloc(&S->d_W, S->nb)) || (rc = dev_alloc(&S->d_cum, S->nb)) ||
+        (rc = dev_alloc(&S->d_cumw, S->nb)) || (rc = dev_alloc(&S->d_blocks, S->blocks.size())) ||
+        (rc = dev_alloc(&S->d_coff, S->colour_off.size())) || (rc = dev_alloc(&S->d_wcol, S->n_windows)) ||
+        (rc = dev_alloc(&S->d_wdur, S->n_windows))) {
+        free_sim_device(S);
+        delete S;
+        return rc;
+    }
+    hipStream_t st = ctx->stream;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(S->d_table, S->table.data(), S->table.size() * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(S->d_blocks, S->blocks.data(), S->blocks.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(S->d_coff, S->colour_off.data(), S->colour_off.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && S->n_windows)
+        e = hipMemcpyAsync(S->d_wcol, S->win_colour.data(), S->n_windows, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && S->n_windows)
+        e = hipMemcpyAsync(S->d_wdur, S->win_dur.data(), S->n_windows * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = launch_init(S->d_lat, N, 0, 0.0, 0, 0, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st); // the host vectors above are pageable
+    if (e != hipSuccess || (rc = reset_counters(S))) {
+        free_sim_device(S);
+        delete S;
+        return e != hipSuccess ? fail(FSKMC_EDEVICE, "sim upload failed: %s", hipGetErrorString(e)) : rc;
+    }
+    *out = S;
+    return FSKMC_OK;
+}
+
+int fskmc_sim_destroy(fskmc_sim* S)
+{
+    if (!S)
+        return FSKMC_OK;
+    (void)hipSetDevice(S->ctx->device);
+    (void)hipStreamSynchronize(S->ctx->stream);
+    free_sim_device(S);
+    delete S;
+    return FSKMC_OK;
+}
+
+int fskmc_sim_attach_device_lattice(fskmc_sim* S, void* dev_ptr, size_t bytes)
+{
+    if (!S || !dev_ptr)
+        return fail(FSKMC_EINVAL, "NULL argument");
+    const size_t N = (size_t)n_sites(S->lat);
+    if (bytes < N)
+        return fail(FSKMC_EINVAL, "buffer of %zu bytes, lattice needs %zu", bytes, N);
+    if (((uintptr_t)dev_ptr) % 16)
+        return fail(FSKMC_EINVAL, "device lattice must be 16-byte aligned");
+    if (dev_ptr == S->d_lat)
+        return FSKMC_OK;
+    HIP_TRY(hipMemcpyAsync(dev_ptr, S->d_lat, N, hipMemcpyDeviceToDevice, S->ctx->stream));
+    HIP_TRY(hipStreamSynchronize(S->ctx->stream));
+    if (S->own_lat)
+        HIP_TRY(hipFree(S->d_lat));
+    S->d_lat = (uint8_t*)dev_ptr;
+    S->own_lat = false;
+    return FSKMC_OK;
+}
+
+int fskmc_sim_init(fskmc_sim* S, int kind, double p)
+{
+    if (!S)
+        return fail(FSKMC_EINVAL, "sim is NULL");
+    if (kind != 0 && kind != 1)
+        return fail(FSKMC_EINVAL, "init kind must be 0 (empty) or 1 (Bernoulli)");
+    if (kind == 1 && !(p >= 0.0 && p <= 1.0))
+        return fail(FSKMC_EINVAL, "Bernoulli p must be in [0,1]");
+    HIP_TRY(launch_init(S->d_lat, n_sites(S->lat), kind, p, S->key.seed, S->key.replica, S->ctx->stream));
+    S->window = 0;
+    return reset_counters(S);
+}
+
+int fskmc_sim_set_lattice(fskmc_sim* S, const uint8_t* host, size_t n)
+{
+    if (!S || !host)
+        return fail(FSKMC_EINVAL, "NULL argument");
+    if (n != (size_t)n_sites(S->lat))
+        return fail(FSKMC_EINVAL, "lattice has %lld sites, got %zu bytes", (long long)n_sites(S->lat), n);
+    const int K = S->model == FSKMC_MODEL_FLIP ? 2 : 3;
+    for (size_t i = 0; i < n; ++i)
+        if (host[i] >= K)
+            return fail(FSKMC_EINVAL, "site %zu has state %d outside [0,%d)", i, (int)host[i], K);
+    HIP_TRY(hipMemcpyAsync(S->d_lat, host, n, hipMemcpyHostToDevice, S->ctx->stream));
+    HIP_TRY(hipStreamSynchronize(S->ctx->stream));
+    return FSKMC_OK;
+}
+
+int fskmc_sim_get_lattice(fskmc_sim* S, uint8_t* host, size_t n)
+{
+    if (!S || !host)
+        return fail(FSKMC_EINVAL, "NULL argument");
+    if (n != (size_t)n_sites(S->lat))
+        return fail(FSKMC_EINVAL, "lattice has %lld sites, got %zu bytes", (long long)n_sites(S->lat), n);
+    HIP_TRY(hipMemcpyAsync(host, S->d_lat, n, hipMemcpyDeviceToHost, S->ctx->stream));
+    HIP_TRY(hipStreamSynchronize(S->ctx->stream));
+    return FSKMC_OK;
+}
+
+int fskmc_sim_advance(fskmc_sim* S, uint64_t n_windows)
+{
+    if (!S)
+        return fail(FSKMC_EINVAL, "sim is NULL");
+    if (n_windows > S->n_windows - S->window)
+        return fail(FSKMC_ESTATE, "only %llu windows left before T", (unsigned long long)(S->n_windows - S->window));
+    for (uint64_t i = 0; i < n_windows; ++i) {
+        int rc = enqueue_window(S, S->window);
+        if (rc)
+            return rc;
+        S->window++;
+    }
+    return FSKMC_OK;
+}
+
+int fskmc_sim_run_to_end(fskmc_sim* S)
+{
+    if (!S)
+        return fail(FSKMC_EINVAL, "sim is NULL");
+    return fskmc_sim_advance(S, S->n_windows - S->window);
+}
+
+int fskmc_sim_windows(const fskmc_sim* S, uint64_t* total, uint64_t* next)
+{
+    if (!S)
+        return fail(FSKMC_EINVAL, "sim is NULL");
+    if (total)
+        *total = S->n_windows;
+    if (next)
+        *next = S->window;
+    return FSKMC_OK;
+}
+
+int fskmc_sim_observe(fskmc_sim* S, fskmc_obs* out)
+{
+    if (!S || !out)
+        return fail(FSKMC_EINVAL, "NULL argument");
+    fskmc_ctx* c = S->ctx;
+    HIP_TRY(launch_fill_u64((uint64_t*)c->d_obs, 9, 0ull, c->stream));
+    HIP_TRY(launch_observe(S->d_lat, S->lat.Lx, S->lat.Ly, S->lat.dim, S->d_cum, S->d_cumw, S->nb, c->d_obs,
+                           c->stream));
+    HIP_TRY(hipMemcpyAsync(c->h_obs, c->d_obs, 9 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    std::memset(out, 0, sizeof *out);
+    out->n_sites = n_sites(S->lat);
+    for (int k = 0; k < 3; ++k) {
+        out->count[k] = (int64_t)c->h_obs[k];
+        out->bonds_equal[k] = (int64_t)c->h_obs[3 + k];
+    }
+    out->bonds_ab = (int64_t)c->h_obs[6];
+    out->events = c->h_obs[7];
+    out->writes = c->h_obs[8];
+    out->block_windows = S->block_windows;
+    out->window = S->window;
+    uint64_t steps = 0;
+    for (uint64_t w = 0; w < S->window; ++w)
+        steps += S->step_end[w];
+    out->steps = steps;
+    out->t = (double)steps * S->sched.dt;
+    return FSKMC_OK;
+}
+
+int fskmc_sim_block_events(fskmc_sim* S, uint32_t* out, size_t n_blocks)
+{
+    if (!S || !out)
+        return fail(FSKMC_EINVAL, "NULL argument");
+    if (n_blocks != (size_t)S->nb)
+        return fail(FSKMC_EINVAL, "sim has %d blocks, got %zu", S->nb, n_blocks);
+    HIP_TRY(hipMemcpyAsync(out, S->d_W, n_blocks * 4, hipMemcpyDeviceToHost, S->ctx->stream));
+    HIP_TRY(hipStreamSynchronize(S->ctx->stream));
+    return FSKMC_OK;
+}
+
+int fskmc_sim_rate_table(const fskmc_sim* S, double* out, size_t n)
+{
+    if (!S || !out)
+        return fail(FSKMC_EINVAL, "NULL argument");
+    if (n < S->table.size())
+        return fail(FSKMC_EINVAL, "table has %zu entries", S->table.size());
+    std::memcpy(out, S->table.data(), S->table.size() * 8);
+    return (int)S->table.size();
+}
+
+int fskmc_sim_get_state(fskmc_sim* S, uint64_t* window, uint8_t* host, size_t n)
+{
+    if (!S || !window || !host)
+        return fail(FSKMC_EINVAL, "NULL argument");
+    int rc = fskmc_sim_get_lattice(S, host, n);
+    if (rc)
+        return rc;
+    *window = S->window;
+    return FSKMC_OK;
+}
+
+int fskmc_sim_set_state(fskmc_sim* S, uint64_t window, const uint8_t* host, size_t n)
+{
+    if (!S || !host)
+        return fail(FSKMC_EINVAL, "NULL argument");
+    if (window > S->n_windows)
+        return fail(FSKMC_EINVAL, "window %llu beyond the schedule (%llu)", (unsigned long long)window,
+                    (unsigned long long)S->n_windows);
+    int rc = fskmc_sim_set_lattice(S, host, n);
+    if (rc)
+        return rc;
+    S->window = window;
+    return reset_counters(S);
+}
+
+size_t fskmc_sim_footprint(const fskmc_lattice* lattice, int model, const fskmc_decomp* decomp,
+                           const fskmc_schedule* schedule)
+{
+    if (!lattice || !decomp || !schedule || lattice->Lx <= 0 || lattice->Ly <= 0 || decomp->bx <= 0 ||
+        decomp->by <= 0 || !(schedule->dt > 0))
+        return 0;
+    const int64_t N = (int64_t)lattice->Lx * lattice->Ly;
+    const int nb = (lattice->Lx / decomp->bx) * (lattice->Ly / decomp->by);
+    const int K = decomp->n_colours;
+    const uint64_t per = schedule->split == FSKMC_STRANG ? 2 * K - 1 : K;
+    const uint64_t nw = (uint64_t)std::floor(schedule->T / schedule->dt + 0.5) * per;
+    return footprint_of(N, model, nb, nw, K);
+}
+
+int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t windows)
+{
+    if (!ctx || (n > 0 && !sims) || n < 0)
+        return fail(FSKMC_EINVAL, "bad arguments");
+    if (n == 0 || windows == 0)
+        return FSKMC_OK;
+    for (int i = 0; i < n; ++i) {
+        if (!sims[i] || sims[i]->ctx != ctx)
+            return fail(FSKMC_EINVAL, "sim %d is NULL or belongs to another context", i);
+        for (int j = 0; j < i; ++j)
+            if (sims[j] == sims[i])
+                return fail(FSKMC_EINVAL, "sim %d appears twice", i);
+    }
+    // group the sims by kernel variant; each group is one launch per step
+    struct Group {
+        int model, P, shape;
+        std::vector<int> idx;
+        uint32_t items = 0;
+        size_t job_off = 0, item_off = 0;
+    };
+    std::vector<Group> groups;
+    for (int i = 0; i < n; ++i) {
+        fskmc_sim* S = sims[i];
+        if (S->window >= S->n_windows)
+            continue;
+        Group* g = nullptr;
+        for (auto& gg : groups)
+            if (gg.model == S->model && gg.P == S->P && gg.shape == S->shape)
+                g = &gg;
+        if (!g) {
+            groups.push_back(Group{S->model, S->P, S->shape, {}, 0, 0, 0});
+            g = &groups.back();
+        }
+        g->idx.push_back(i);
+    }
+    size_t n_jobs = 0, n_items = 0;
+    for (auto& g : groups) {
+        g.job_off = n_jobs;
+        g.item_off = n_items;
+        for (int i : g.idx)
+            g.items += (uint32_t)sims[i]->max_per_colour;
+        n_jobs += g.idx.size();
+        n_items += g.items;
+    }
+    if (n_jobs == 0)
+        return FSKMC_OK;
+    if (n_jobs > ctx->cap_jobs) {
+        (void)hipFree(ctx->d_jobs);
+        ctx->d_jobs = nullptr;
+        ctx->cap_jobs = 0;
+        int rc = dev_alloc(&ctx->d_jobs, n_jobs * 2);
+        if (rc)
+            return rc;
+        ctx->cap_jobs = n_jobs * 2;
+    }
+    if (n_items > ctx->cap_items) {
+        (void)hipFree(ctx->d_items);
+        ctx->d_items = nullptr;
+        ctx->cap_items = 0;
+        int rc = dev_alloc(&ctx->d_items, n_items * 2);
+        if (rc)
+            return rc;
+        ctx->cap_items = n_items * 2;
+    }
+    const size_t bytes = n_jobs * sizeof(JobDesc) + n_items * 4;
+    HIP_TRY(hipEventSynchronize(ctx->stage_free)); // previous upload has left the staging buffer
+    if (bytes > ctx->cap_stage) {
+        (void)hipHostFree(ctx->h_stage);
+        ctx->h_stage = nullptr;
+        ctx->cap_stage = 0;
+        if (hipHostMalloc((void**)&ctx->h_stage, bytes * 2, hipHostMallocDefault) != hipSuccess)
+            return fail(FSKMC_ENOMEM, "pinned staging of %zu bytes failed", bytes * 2);
+        ctx->cap_stage = bytes * 2;
+    }
+    JobDesc* hj = (JobDesc*)ctx->h_stage;
+    uint32_t* hi = (uint32_t*)(ctx->h_stage + n_jobs * sizeof(JobDesc));
+    for (auto& g : groups) {
+        uint32_t item = 0;
+        for (size_t k = 0; k < g.idx.size(); ++k) {
+            fskmc_sim* S = sims[g.idx[k]];
+            JobDesc& d = hj[g.job_off + k];
+            d.lat = S->d_lat;
+            d.table = S->d_table;
+            d.W_last = S->d_W;
+            d.cum_events = S->d_cum;
+            d.cum_writes = S->d_cumw;
+            d.blocks = S->d_blocks;
+            d.colour_off = S->d_coff;
+            d.win_colour = S->d_wcol;
+            d.win_dur = S->d_wdur;
+            d.n_windows = S->n_windows;
+            d.base_window = S->window;
+            d.Lx = S->lat.Lx;
+            d.Ly = S->lat.Ly;
+            d.NBX = S->NBX;
+            d.k0 = S->key.seed;
+            d.k1 = S->key.replica;
+            d.item_begin = item;
+            d.n_items = (uint32_t)S->max_per_colour;
+            d.pad = 0;
+            for (int q = 0; q < S->max_per_colour; ++q)
+                hi[g.item_off + item + q] = (uint32_t)k;
+            item += (uint32_t)S->max_per_colour;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->d_jobs, hj, n_jobs * sizeof(JobDesc), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(ctx->d_items, hi, n_items * 4, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipEventRecord(ctx->stage_free, ctx->stream));
+    for (uint32_t step = 0; step < windows; ++step) {
+        for (auto& g : groups) {
+            const long tk = timing_begin(ctx);
+            HIP_TRY(launch_sweep_batched(g.model, g.P, g.shape, ctx->wpg, ctx->d_jobs + g.job_off,
+                                         ctx->d_items + g.item_off, g.items, step, ctx->stream));
+            timing_end(ctx, tk);
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        fskmc_sim* S = sims[i];
+        const uint64_t end = std::min<uint64_t>(S->n_windows, S->window + windows);
+        for (uint64_t w = S->window; w < end; ++w) {
+            const int c = S->win_colour[w];
+            S->block_windows += (uint64_t)(S->colour_off[c + 1] - S->colour_off[c]);
+        }
+        S->window = end;
+    }
+    return FSKMC_OK;
+}
+
+}  // extern "C"

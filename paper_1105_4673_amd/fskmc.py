@@ -1,0 +1,318 @@
+"""ctypes binding of libfskmc (include/fskmc.h).
+
+The functions below carry the C names and only marshal arguments: every step
+of the fractional-step path runs in the HIP library.  Importing this module
+raises if libfskmc.so has not been built; there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfskmc.so")
+
+FSKMC_OK, FSKMC_EINVAL, FSKMC_ENOMEM, FSKMC_EDEVICE, FSKMC_EDECOMP, FSKMC_EBUSY, FSKMC_ESTATE = 0, -1, -2, -3, -4, -5, -6
+FSKMC_MODEL_FLIP, FSKMC_MODEL_ZGB = 1, 2
+FSKMC_LIE, FSKMC_STRANG, FSKMC_RANDOM = 0, 1, 2
+
+ERRORS = {FSKMC_EINVAL: "EINVAL", FSKMC_ENOMEM: "ENOMEM", FSKMC_EDEVICE: "EDEVICE", FSKMC_EDECOMP: "EDECOMP",
+          FSKMC_EBUSY: "EBUSY", FSKMC_ESTATE: "ESTATE"}
+
+
+class FskmcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class fskmc_lattice(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("Lx", ctypes.c_int), ("Ly", ctypes.c_int)]
+
+
+class fskmc_flip_params(ctypes.Structure):
+    _fields_ = [("k_a", ctypes.c_double), ("k_d", ctypes.c_double), ("J", ctypes.c_double),
+                ("h", ctypes.c_double), ("beta", ctypes.c_double)]
+
+
+class fskmc_zgb_params(ctypes.Structure):
+    _fields_ = [("y", ctypes.c_double), ("k_r", ctypes.c_double), ("D", ctypes.c_double)]
+
+
+class fskmc_decomp(ctypes.Structure):
+    _fields_ = [("bx", ctypes.c_int), ("by", ctypes.c_int), ("n_colours", ctypes.c_int),
+                ("colour_map", ctypes.POINTER(ctypes.c_int))]
+
+
+class fskmc_schedule(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("T", ctypes.c_double), ("split", ctypes.c_int)]
+
+
+class fskmc_key(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint32), ("replica", ctypes.c_uint32)]
+
+
+class fskmc_obs(ctypes.Structure):
+    _fields_ = [("n_sites", ctypes.c_int64), ("count", ctypes.c_int64 * 3), ("bonds_equal", ctypes.c_int64 * 3),
+                ("bonds_ab", ctypes.c_int64), ("window", ctypes.c_uint64), ("steps", ctypes.c_uint64),
+                ("events", ctypes.c_uint64), ("block_windows", ctypes.c_uint64), ("writes", ctypes.c_uint64),
+                ("t", ctypes.c_double)]
+
+
+SYMBOLS = [
+    "fskmc_ctx_create", "fskmc_ctx_destroy", "fskmc_last_error", "fskmc_sim_create", "fskmc_sim_destroy",
+    "fskmc_sim_attach_device_lattice", "fskmc_sim_init", "fskmc_sim_set_lattice", "fskmc_sim_get_lattice",
+    "fskmc_sim_advance", "fskmc_sim_run_to_end", "fskmc_sim_windows", "fskmc_sim_observe",
+    "fskmc_sim_block_events", "fskmc_sim_rate_table", "fskmc_sim_get_state", "fskmc_sim_set_state",
+    "fskmc_sim_footprint", "fskmc_batch_advance", "fskmc_sync", "fskmc_ctx_set_waves_per_group",
+    "fskmc_ctx_set_kernel_timing", "fskmc_ctx_read_kernel_timing",
+]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libfskmc.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    L.fskmc_last_error.restype = ctypes.c_char_p
+    L.fskmc_ctx_create.argtypes = [ctypes.c_int, vp, P(vp)]
+    L.fskmc_ctx_destroy.argtypes = [vp]
+    L.fskmc_ctx_set_waves_per_group.argtypes = [vp, ctypes.c_int]
+    L.fskmc_sync.argtypes = [vp]
+    L.fskmc_ctx_set_kernel_timing.argtypes = [vp, ctypes.c_int]
+    L.fskmc_ctx_read_kernel_timing.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_uint64)]
+    L.fskmc_sim_create.argtypes = [vp, P(fskmc_lattice), ctypes.c_int, vp, P(fskmc_decomp), P(fskmc_schedule),
+                                   fskmc_key, P(vp)]
+    L.fskmc_sim_destroy.argtypes = [vp]
+    L.fskmc_sim_attach_device_lattice.argtypes = [vp, vp, ctypes.c_size_t]
+    L.fskmc_sim_init.argtypes = [vp, ctypes.c_int, ctypes.c_double]
+    L.fskmc_sim_set_lattice.argtypes = [vp, P(ctypes.c_uint8), ctypes.c_size_t]
+    L.fskmc_sim_get_lattice.argtypes = [vp, P(ctypes.c_uint8), ctypes.c_size_t]
+    L.fskmc_sim_advance.argtypes = [vp, ctypes.c_uint64]
+    L.fskmc_sim_run_to_end.argtypes = [vp]
+    L.fskmc_sim_windows.argtypes = [vp, P(ctypes.c_uint64), P(ctypes.c_uint64)]
+    L.fskmc_sim_observe.argtypes = [vp, P(fskmc_obs)]
+    L.fskmc_sim_block_events.argtypes = [vp, P(ctypes.c_uint32), ctypes.c_size_t]
+    L.fskmc_sim_rate_table.argtypes = [vp, P(ctypes.c_double), ctypes.c_size_t]
+    L.fskmc_sim_get_state.argtypes = [vp, P(ctypes.c_uint64), P(ctypes.c_uint8), ctypes.c_size_t]
+    L.fskmc_sim_set_state.argtypes = [vp, ctypes.c_uint64, P(ctypes.c_uint8), ctypes.c_size_t]
+    L.fskmc_sim_footprint.argtypes = [P(fskmc_lattice), ctypes.c_int, P(fskmc_decomp), P(fskmc_schedule)]
+    L.fskmc_sim_footprint.restype = ctypes.c_size_t
+    L.fskmc_batch_advance.argtypes = [vp, P(vp), ctypes.c_int, ctypes.c_uint32]
+    return L
+
+
+lib = _load()
+
+
+def _check(rc):
+    if rc < 0:
+        raise FskmcError(rc, lib.fskmc_last_error().decode())
+    return rc
+
+
+def _u8p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+# --- thin wrappers with the C names -----------------------------------------
+def fskmc_ctx_create(device=0, hip_stream=None):
+    out = ctypes.c_void_p()
+    _check(lib.fskmc_ctx_create(device, hip_stream, ctypes.byref(out)))
+    return out
+
+
+def fskmc_ctx_destroy(ctx):
+    _check(lib.fskmc_ctx_destroy(ctx))
+
+
+def fskmc_ctx_set_waves_per_group(ctx, waves):
+    _check(lib.fskmc_ctx_set_waves_per_group(ctx, waves))
+
+
+def fskmc_sync(ctx):
+    _check(lib.fskmc_sync(ctx))
+
+
+def fskmc_ctx_set_kernel_timing(ctx, stride):
+    _check(lib.fskmc_ctx_set_kernel_timing(ctx, stride))
+
+
+def fskmc_ctx_read_kernel_timing(ctx):
+    ms, n = ctypes.c_double(), ctypes.c_uint64()
+    _check(lib.fskmc_ctx_read_kernel_timing(ctx, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def _decomp(bx, by, n_colours, colour_map):
+    cm = None
+    keep = None
+    if colour_map is not None:
+        keep = np.ascontiguousarray(colour_map, dtype=np.int32)
+        cm = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    return fskmc_decomp(bx, by, n_colours, cm), keep
+
+
+def fskmc_sim_create(ctx, dim, Lx, Ly, model, params, bx, by, n_colours, dt, T, split, seed, replica,
+                     colour_map=None):
+    lat = fskmc_lattice(dim, Lx, Ly)
+    if model == FSKMC_MODEL_FLIP:
+        p = fskmc_flip_params(*params)
+    else:
+        p = fskmc_zgb_params(*params)
+    dec, _keep = _decomp(bx, by, n_colours, colour_map)
+    sch = fskmc_schedule(dt, T, split)
+    out = ctypes.c_void_p()
+    _check(lib.fskmc_sim_create(ctx, ctypes.byref(lat), model, ctypes.cast(ctypes.byref(p), ctypes.c_void_p),
+                                ctypes.byref(dec), ctypes.byref(sch), fskmc_key(seed, replica), ctypes.byref(out)))
+    return out
+
+
+def fskmc_sim_destroy(sim):
+    _check(lib.fskmc_sim_destroy(sim))
+
+
+def fskmc_sim_attach_device_lattice(sim, dev_ptr, nbytes):
+    _check(lib.fskmc_sim_attach_device_lattice(sim, ctypes.c_void_p(dev_ptr), nbytes))
+
+
+def fskmc_sim_init(sim, kind, p=0.5):
+    _check(lib.fskmc_sim_init(sim, kind, p))
+
+
+def fskmc_sim_set_lattice(sim, host):
+    a = np.ascontiguousarray(host, dtype=np.uint8).ravel()
+    _check(lib.fskmc_sim_set_lattice(sim, _u8p(a), a.size))
+
+
+def fskmc_sim_get_lattice(sim, n):
+    a = np.empty(n, np.uint8)
+    _check(lib.fskmc_sim_get_lattice(sim, _u8p(a), n))
+    return a
+
+
+def fskmc_sim_advance(sim, n_windows):
+    _check(lib.fskmc_sim_advance(sim, n_windows))
+
+
+def fskmc_sim_run_to_end(sim):
+    _check(lib.fskmc_sim_run_to_end(sim))
+
+
+def fskmc_sim_windows(sim):
+    tot, nxt = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib.fskmc_sim_windows(sim, ctypes.byref(tot), ctypes.byref(nxt)))
+    return tot.value, nxt.value
+
+
+def fskmc_sim_observe(sim):
+    o = fskmc_obs()
+    _check(lib.fskmc_sim_observe(sim, ctypes.byref(o)))
+    return {"n_sites": o.n_sites, "count": list(o.count), "bonds_equal": list(o.bonds_equal),
+            "bonds_ab": o.bonds_ab, "window": o.window, "steps": o.steps, "events": o.events,
+            "block_windows": o.block_windows, "writes": o.writes, "t": o.t}
+
+
+def fskmc_sim_block_events(sim, n_blocks):
+    a = np.empty(n_blocks, np.uint32)
+    _check(lib.fskmc_sim_block_events(sim, a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), n_blocks))
+    return a
+
+
+def fskmc_sim_rate_table(sim, cap=243 * 14):
+    a = np.empty(cap, np.float64)
+    n = _check(lib.fskmc_sim_rate_table(sim, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), cap))
+    return a[:n].copy()
+
+
+def fskmc_sim_get_state(sim, n):
+    a = np.empty(n, np.uint8)
+    w = ctypes.c_uint64()
+    _check(lib.fskmc_sim_get_state(sim, ctypes.byref(w), _u8p(a), n))
+    return w.value, a
+
+
+def fskmc_sim_set_state(sim, window, host):
+    a = np.ascontiguousarray(host, dtype=np.uint8).ravel()
+    _check(lib.fskmc_sim_set_state(sim, window, _u8p(a), a.size))
+
+
+def fskmc_sim_footprint(dim, Lx, Ly, model, bx, by, n_colours, dt, T, split):
+    lat = fskmc_lattice(dim, Lx, Ly)
+    dec, _ = _decomp(bx, by, n_colours, None)
+    sch = fskmc_schedule(dt, T, split)
+    return lib.fskmc_sim_footprint(ctypes.byref(lat), model, ctypes.byref(dec), ctypes.byref(sch))
+
+
+def fskmc_batch_advance(ctx, sims, windows):
+    arr = (ctypes.c_void_p * len(sims))(*[s.value if isinstance(s, ctypes.c_void_p) else s for s in sims])
+    _check(lib.fskmc_batch_advance(ctx, arr, len(sims), windows))
+
+
+# --- convenience object ------------------------------------------------------
+class Sim:
+    """One lattice simulation on the GPU.
+
+    kind 'flip': params (k_a, k_d, J, h, beta); kind 'zgb': params (y, k_r, D).
+    """
+
+    def __init__(self, ctx, kind, Lx, Ly=1, params=(1.0, 1.0, 0.0, 0.0, 1.0), b=None, bx=None, by=None,
+                 n_colours=2, dt=0.1, T=1.0, split=FSKMC_LIE, seed=0, replica=0, colour_map=None, dim=None):
+        self.ctx = ctx
+        self.kind = kind
+        self.dim = dim if dim is not None else (1 if Ly == 1 else 2)
+        self.Lx, self.Ly = Lx, Ly
+        if b is not None:
+            bx, by = (b, b) if self.dim == 2 else (b, 1)
+        self.bx, self.by = bx, by
+        self.n_colours = n_colours
+        self.model = FSKMC_MODEL_FLIP if kind == "flip" else FSKMC_MODEL_ZGB
+        self.handle = fskmc_sim_create(ctx, self.dim, Lx, Ly, self.model, params, bx, by, n_colours, dt, T, split,
+                                       seed, replica, colour_map)
+        self.N = Lx * Ly
+        self.nb = (Lx // bx) * (Ly // by)
+
+    def close(self):
+        if self.handle is not None:
+            fskmc_sim_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, kind, p=0.5):
+        fskmc_sim_init(self.handle, kind, p)
+
+    def set_lattice(self, host):
+        fskmc_sim_set_lattice(self.handle, host)
+
+    def lattice(self):
+        return fskmc_sim_get_lattice(self.handle, self.N)
+
+    def advance(self, n):
+        fskmc_sim_advance(self.handle, n)
+
+    def run_to_end(self):
+        fskmc_sim_run_to_end(self.handle)
+
+    def windows(self):
+        return fskmc_sim_windows(self.handle)
+
+    def observe(self):
+        return fskmc_sim_observe(self.handle)
+
+    def block_events(self):
+        return fskmc_sim_block_events(self.handle, self.nb)
+
+    def rate_table(self):
+        return fskmc_sim_rate_table(self.handle)
+
+    def get_state(self):
+        return fskmc_sim_get_state(self.handle, self.N)
+
+    def set_state(self, window, host):
+        fskmc_sim_set_state(self.handle, window, host)

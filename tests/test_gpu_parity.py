@@ -1,0 +1,331 @@
+"""Parity of the HIP fractional-step sweep with the CPU oracle (needs a GPU).
+
+Bit-exact: the lattice after every window (small cases) or after sampled
+windows (full-size cases), the per-block event counts W of every active block,
+the host-built rate tables, the Bernoulli initial state and the integer
+observables.  Every call goes through the C ABI of libfskmc.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+FLIP = "flip"
+ZGB = "zgb"
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_1105_4673_amd import fskmc
+    return fskmc
+
+
+@pytest.fixture(scope="module")
+def ctx(F):
+    c = F.fskmc_ctx_create(0)
+    yield c
+    F.fskmc_ctx_destroy(c)
+
+
+def _orc_model(orc, kind, Lx, Ly, params):
+    if kind == FLIP:
+        k_a, k_d, J, h, beta = params
+        return orc.Model(FLIP, Lx, Ly, k_a=k_a, k_d=k_d, J=J, h=h, beta=beta)
+    y, k_r, D = params
+    return orc.Model(ZGB, Lx, Ly, y=y, k_r=k_r, D=D)
+
+
+def _split_code(name):
+    return {"lie": 0, "strang": 1, "random": 2}[name]
+
+
+class Pair:
+    """A GPU simulation and its oracle twin on the same inputs."""
+
+    def __init__(self, F, orc, ctx, kind, Lx, Ly, params, b, ncol, dt, T, split, seed=0, replica=0,
+                 init="empty", lattice0=None, colour_map=None):
+        self.F, self.orc = F, orc
+        self.kind = kind
+        dim = 1 if Ly == 1 else 2
+        self.bx, self.by = (b, b) if dim == 2 else (b, 1)
+        self.sim = F.Sim(ctx, kind, Lx, Ly, params, bx=self.bx, by=self.by, n_colours=ncol, dt=dt, T=T,
+                         split=_split_code(split), seed=seed, replica=replica, colour_map=colour_map)
+        self.model = _orc_model(orc, kind, Lx, Ly, params)
+        self.N = Lx * Ly
+        self.seed, self.replica, self.ncol = seed, replica, ncol
+        self.cmap = (np.asarray(colour_map, np.int32) if colour_map is not None
+                     else orc.colour_map(self.model, self.bx, self.by, ncol))
+        self.cols, self.durs, self.ends = orc.schedule(_split_code(split), ncol, dt, T, seed, replica)
+        if init == "empty":
+            self.sim.init(0)
+            self.lat = np.zeros(self.N, np.uint8)
+        elif init == "bernoulli":
+            self.sim.init(1, 0.5)
+            self.lat = orc.init_bernoulli(self.N, 0.5, seed, replica)
+        else:
+            self.lat = np.asarray(lattice0, np.uint8).ravel().copy()
+            self.sim.set_lattice(self.lat)
+        self.w = 0
+
+    def step_compare_each(self, n):
+        """Advance n windows one by one; compare the lattice and W each time."""
+        res = self.orc.fs_run(self.model, self.lat, self.bx, self.by, self.cmap, self.ncol,
+                              self.cols[self.w:self.w + n], self.durs[self.w:self.w + n], self.seed,
+                              self.replica, w0=self.w, want_W=True, want_snap=True)
+        events = 0
+        for i in range(n):
+            self.sim.advance(1)
+            got = self.sim.lattice()
+            want = res["snap"][i]
+            assert np.array_equal(got, want), (self.w + i, int((got != want).sum()))
+            active = self.cmap == self.cols[self.w + i]
+            W = self.sim.block_events()
+            np.testing.assert_array_equal(W[active], res["W"][i][active])
+            events += int(res["W"][i].sum())
+        self.lat = res["lattice"]
+        self.w += n
+        return events
+
+    def step_compare_end(self, n):
+        """Advance n windows in one call; compare the final lattice and events."""
+        res = self.orc.fs_run(self.model, self.lat, self.bx, self.by, self.cmap, self.ncol,
+                              self.cols[self.w:self.w + n], self.durs[self.w:self.w + n], self.seed,
+                              self.replica, w0=self.w, want_W=True)
+        self.sim.advance(n)
+        got = self.sim.lattice()
+        assert np.array_equal(got, res["lattice"]), int((got != res["lattice"]).sum())
+        W = self.sim.block_events()
+        last = self.cols[self.w + n - 1]
+        active = self.cmap == last
+        np.testing.assert_array_equal(W[active], res["W"][n - 1][active])
+        self.lat = res["lattice"]
+        self.w += n
+        return res["events"]
+
+
+def test_rate_tables_bitwise(F, orc, ctx):
+    cases = [(FLIP, 64, 64, (1.0, 1.0, 1.0, 0.0, 1.0), 8, 2), (FLIP, 256, 1, (0.3, 2.5, 2.0, -1.0, 1.7), 64, 2),
+             (FLIP, 64, 64, (1.0, 1.0, 0.5, 0.3, 3.0), 16, 2), (ZGB, 64, 64, (0.53, 1000.0, 10.0), 32, 4),
+             (ZGB, 64, 64, (0.3, 7.5, 0.0), 16, 4)]
+    for kind, Lx, Ly, prm, b, ncol in cases:
+        p = Pair(F, orc, ctx, kind, Lx, Ly, prm, b, ncol, 0.1, 0.2, "lie")
+        got = p.sim.rate_table()
+        want = orc.rate_table(p.model)
+        assert got.tobytes() == want.tobytes(), kind
+        p.sim.close()
+
+
+def test_bernoulli_init_bitwise(F, orc, ctx):
+    for (Lx, Ly, seed, rep) in [(64, 64, 0, 0), (1024, 1024, 0, 3), (512, 1, 7, 11)]:
+        s = F.Sim(ctx, FLIP, Lx, Ly, (1, 1, 1, 0, 1), b=8 if Ly > 1 else 64, dt=0.1, T=0.1, seed=seed, replica=rep)
+        s.init(1, 0.5)
+        np.testing.assert_array_equal(s.lattice(), orc.init_bernoulli(Lx * Ly, 0.5, seed, rep))
+        s.init(1, 0.3)
+        np.testing.assert_array_equal(s.lattice(), orc.init_bernoulli(Lx * Ly, 0.3, seed, rep))
+        s.close()
+
+
+def test_config0_every_window(F, orc, ctx):
+    """64x64, J=1, 8x8 blocks, 2 colours, Lie dt=0.1, T=10, empty start, seed 0:
+    the whole run, lattice and block counts after every window."""
+    p = Pair(F, orc, ctx, FLIP, 64, 64, (1.0, 1.0, 1.0, 0.0, 1.0), 8, 2, 0.1, 10.0, "lie")
+    total, nxt = p.sim.windows()
+    assert total == 200 and nxt == 0
+    ev = p.step_compare_each(200)
+    obs = p.sim.observe()
+    want = orc.observe(p.model, p.lat)
+    assert obs["count"][:2] == list(want[:2]) and obs["bonds_equal"][1] == want[4]
+    assert obs["events"] == ev and obs["window"] == 200 and obs["steps"] == 100
+    assert abs(obs["t"] - 10.0) < 1e-12
+    with pytest.raises(F.FskmcError):
+        p.sim.advance(1)
+
+
+@pytest.mark.parametrize("wpg", [1, 2, 4, 8])
+def test_waves_per_group_is_result_neutral(F, orc, ctx, wpg):
+    F.fskmc_ctx_set_waves_per_group(ctx, wpg)
+    try:
+        p = Pair(F, orc, ctx, FLIP, 128, 128, (1.0, 1.0, 0.5, 0.0, 1.0), 16, 2, 0.5, 5.0, "strang",
+                 init="bernoulli", seed=3, replica=1)
+        p.step_compare_end(15)
+    finally:
+        F.fskmc_ctx_set_waves_per_group(ctx, 2)
+
+
+@pytest.mark.parametrize("J,dt,split", [(0.5, 1.0, "lie"), (1.0, 0.1, "lie"), (2.0, 0.1, "strang"),
+                                        (1.0, 0.01, "strang"), (0.5, 1.0, "random")])
+def test_config1_shape_small(F, orc, ctx, J, dt, split):
+    """The 16x16-block Ising sweep of the 1024^2 workload on a 256^2 lattice,
+    every window, several (J, dt, split)."""
+    p = Pair(F, orc, ctx, FLIP, 256, 256, (1.0, 1.0, J, 0.0, 1.0), 16, 2, dt, 100.0, split, init="bernoulli",
+             seed=0, replica=5)
+    p.step_compare_each(12)
+
+
+def test_config1_full_size_sampled(F, orc, ctx):
+    """1024^2, J=1, Lie dt=0.1 from Bernoulli(1/2): every window of the first
+    step compared, then batches of windows compared at their ends."""
+    p = Pair(F, orc, ctx, FLIP, 1024, 1024, (1.0, 1.0, 1.0, 0.0, 1.0), 16, 2, 0.1, 100.0, "lie",
+             init="bernoulli", seed=0, replica=0)
+    p.step_compare_each(2)
+    p.step_compare_end(6)
+
+
+def test_config1_full_size_long_window(F, orc, ctx):
+    """1024^2, J=0.5, dt=1 (about 80 events per block-window)."""
+    p = Pair(F, orc, ctx, FLIP, 1024, 1024, (1.0, 1.0, 0.5, 0.0, 1.0), 16, 2, 1.0, 100.0, "lie",
+             init="bernoulli", seed=0, replica=2)
+    p.step_compare_each(2)
+
+
+@pytest.mark.parametrize("b", [8, 16, 32])
+def test_flip_block_sizes(F, orc, ctx, b):
+    p = Pair(F, orc, ctx, FLIP, 4 * b * 2, 2 * b * 2, (0.7, 1.3, 1.2, -0.4, 1.1), b, 2, 0.4, 4.0, "strang",
+             init="bernoulli", seed=9, replica=b)
+    p.step_compare_each(9)
+
+
+@pytest.mark.parametrize("b", [64, 256, 1024])
+def test_flip_1d_rows(F, orc, ctx, b):
+    p = Pair(F, orc, ctx, FLIP, 8 * b, 1, (1.0, 1.0, 1.0, -0.5, 1.0), b, 2, 1.0, 10.0, "lie", init="bernoulli",
+             seed=1, replica=b)
+    p.step_compare_each(8)
+
+
+@pytest.mark.parametrize("y,D,split", [(0.5, 10.0, "strang"), (0.53, 0.0, "strang"), (0.3, 10.0, "lie")])
+def test_reaction_model_4_colours(F, orc, ctx, y, D, split):
+    """3-state A/B reaction model, 32x32 blocks, 4 colours, pair events that
+    write into the halo, stiff k_r = 1e3."""
+    p = Pair(F, orc, ctx, ZGB, 256, 256, (y, 1000.0, D), 32, 4, 0.05, 10.0, split, seed=0, replica=1)
+    p.step_compare_each(14)
+    p.step_compare_end(14)
+    obs = p.sim.observe()
+    want = orc.observe(p.model, p.lat)
+    assert obs["count"] == list(want[:3]) and obs["bonds_equal"] == list(want[3:6]) and obs["bonds_ab"] == want[6]
+
+
+@pytest.mark.parametrize("b", [8, 16])
+def test_reaction_model_small_blocks(F, orc, ctx, b):
+    p = Pair(F, orc, ctx, ZGB, 128, 128, (0.45, 40.0, 3.0), b, 4, 0.1, 2.0, "strang", seed=4, replica=b)
+    p.step_compare_each(14)
+
+
+def test_config2_full_size_first_windows(F, orc, ctx):
+    """4096^2 reaction lattice, 32x32 blocks, Strang dt=0.05: the first two
+    windows compared in full."""
+    p = Pair(F, orc, ctx, ZGB, 4096, 4096, (0.5, 1000.0, 10.0), 32, 4, 0.05, 10.0, "strang", seed=0, replica=0)
+    p.step_compare_each(2)
+
+
+def test_edge_zero_total_rate(F, orc, ctx):
+    """Blocks whose total rate is zero draw nothing: an all-B reaction lattice
+    and an empty lattice without adsorption."""
+    p = Pair(F, orc, ctx, ZGB, 64, 64, (0.5, 1000.0, 10.0), 16, 4, 0.1, 1.0, "lie", init="given",
+             lattice0=np.full(64 * 64, 2, np.uint8))
+    p.step_compare_each(4)
+    assert np.all(p.sim.block_events() == 0)
+    q = Pair(F, orc, ctx, FLIP, 64, 64, (0.0, 1.0, 1.0, 0.0, 1.0), 8, 2, 0.1, 1.0, "lie")
+    q.step_compare_each(4)
+    assert q.sim.observe()["events"] == 0
+
+
+def test_edge_ragged_custom_colouring(F, orc, ctx):
+    """A 3-colour map with unequal colour classes on a 1D ring (NBX = 10):
+    colours 0 and 1 have four blocks, colour 2 has two."""
+    cmap = np.array([0, 1, 2, 0, 1, 2, 0, 1, 0, 1], np.int32)
+    assert orc.decomp_check(orc.Model(FLIP, 640, 1), 64, 1, cmap, 3) == 0
+    p = Pair(F, orc, ctx, FLIP, 640, 1, (1.0, 1.0, 1.0, 0.0, 1.0), 64, 3, 0.5, 5.0, "strang", init="bernoulli",
+             colour_map=cmap)
+    p.step_compare_each(25)
+
+
+def test_edge_invalid_inputs(F, ctx):
+    E = F.FskmcError
+    with pytest.raises(E) as ei:  # pair events with a 2-colour checkerboard
+        F.Sim(ctx, ZGB, 64, 64, (0.5, 1000.0, 0.0), b=16, n_colours=2, dt=0.1, T=1.0)
+    assert ei.value.code == F.FSKMC_EDECOMP
+    with pytest.raises(E):  # T/dt not an integer
+        F.Sim(ctx, FLIP, 64, 64, (1, 1, 1, 0, 1), b=8, dt=0.3, T=1.0)
+    with pytest.raises(E):  # unsupported block
+        F.Sim(ctx, FLIP, 60, 60, (1, 1, 1, 0, 1), b=12, dt=0.1, T=1.0)
+    with pytest.raises(E):  # odd number of blocks breaks the 2-colour checkerboard
+        F.Sim(ctx, FLIP, 24, 24, (1, 1, 1, 0, 1), b=8, dt=0.1, T=1.0)
+    s = F.Sim(ctx, FLIP, 64, 64, (1, 1, 1, 0, 1), b=8, dt=0.1, T=0.1)
+    with pytest.raises(E):  # state outside the spin space
+        s.set_lattice(np.full(4096, 2, np.uint8))
+    s.close()
+
+
+def test_edge_zero_length_schedule(F, ctx):
+    s = F.Sim(ctx, FLIP, 64, 64, (1, 1, 1, 0, 1), b=8, dt=0.1, T=0.0)
+    assert s.windows() == (0, 0)
+    s.run_to_end()
+    assert s.observe()["count"][0] == 4096
+    s.close()
+
+
+def test_checkpoint_resume_bitwise(F, orc, ctx):
+    kw = dict(kind=FLIP, Lx=256, Ly=256, params=(1.0, 1.0, 0.7, 0.1, 1.0), b=16, n_colours=2, dt=0.2, T=4.0,
+              split=F.FSKMC_STRANG, seed=2, replica=4)
+    a = F.Sim(ctx, **kw)
+    a.init(1, 0.5)
+    a.advance(17)
+    w, lat = a.get_state()
+    assert w == 17
+    a.run_to_end()
+    b = F.Sim(ctx, **kw)
+    b.set_state(w, lat)
+    b.run_to_end()
+    np.testing.assert_array_equal(a.lattice(), b.lattice())
+    a.close()
+    b.close()
+
+
+def test_attach_torch_lattice(F, orc, ctx):
+    import torch
+    t = torch.zeros(128 * 128, dtype=torch.uint8, device="cuda")
+    s = F.Sim(ctx, FLIP, 128, 128, (1.0, 1.0, 1.0, 0.0, 1.0), b=16, dt=0.1, T=1.0, seed=0, replica=8)
+    F.fskmc_sim_attach_device_lattice(s.handle, t.data_ptr(), t.numel())
+    s.init(1, 0.5)
+    s.run_to_end()
+    F.fskmc_sync(ctx)
+    model = orc.Model(FLIP, 128, 128, J=1.0)
+    cols, durs, _ = orc.schedule(0, 2, 0.1, 1.0)
+    res = orc.fs_run(model, orc.init_bernoulli(128 * 128, 0.5, 0, 8), 16, 16, orc.colour_map(model, 16, 16, 2), 2,
+                     cols, durs, 0, 8)
+    np.testing.assert_array_equal(t.cpu().numpy(), res["lattice"])
+    s.close()
+
+
+def test_batch_equals_alone(F, orc, ctx):
+    """Sims of different sizes, models and schedules advanced together in one
+    batched launch per window give the same bits as each advanced alone."""
+    specs = [
+        dict(kind=FLIP, Lx=128, Ly=128, params=(1.0, 1.0, 1.5, -0.5, 1.0), b=16, n_colours=2, dt=0.1, T=2.0,
+             split=0, seed=0, replica=1),
+        dict(kind=FLIP, Lx=256, Ly=256, params=(1.0, 1.0, 0.3, 0.8, 1.0), b=16, n_colours=2, dt=0.2, T=2.0,
+             split=1, seed=0, replica=2),
+        dict(kind=FLIP, Lx=64, Ly=64, params=(1.0, 1.0, 1.0, 0.0, 1.0), b=8, n_colours=2, dt=0.1, T=10.0,
+             split=0, seed=0, replica=3),
+        dict(kind=ZGB, Lx=128, Ly=128, params=(0.5, 1000.0, 10.0), b=32, n_colours=4, dt=0.05, T=1.0, split=1,
+             seed=0, replica=4),
+        dict(kind=FLIP, Lx=512, Ly=1, params=(1.0, 1.0, 1.0, 0.0, 1.0), b=64, n_colours=2, dt=1.0, T=5.0,
+             split=0, seed=0, replica=5),
+    ]
+    alone, batch = [], []
+    for sp in specs:
+        a = F.Sim(ctx, **sp)
+        b = F.Sim(ctx, **sp)
+        a.init(1, 0.5)
+        b.init(1, 0.5)
+        a.run_to_end()
+        alone.append(a)
+        batch.append(b)
+    handles = [b.handle for b in batch]
+    while any(b.windows()[1] < b.windows()[0] for b in batch):
+        F.fskmc_batch_advance(ctx, handles, 7)
+    for a, b in zip(alone, batch):
+        np.testing.assert_array_equal(a.lattice(), b.lattice())
+        assert a.observe()["events"] == b.observe()["events"]
+        a.close()
+        b.close()
