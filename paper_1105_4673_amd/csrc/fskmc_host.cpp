@@ -108,9 +108,7 @@ struct fskmc_sim {
     uint8_t* d_lat = nullptr;
     bool own_lat = true;
     double* d_table = nullptr;
-    uint32_t* d_W = nullptr;
-    uint64_t* d_cum = nullptr;
-    uint32_t* d_cumw = nullptr;
+    BlockCount* d_cnt = nullptr;
     int32_t* d_blocks = nullptr;
     int32_t* d_coff = nullptr;
     int8_t* d_wcol = nullptr;
@@ -323,9 +321,7 @@ void free_sim_device(fskmc_sim* S)
     if (S->own_lat && S->d_lat)
         (void)hipFree(S->d_lat);
     (void)hipFree(S->d_table);
-    (void)hipFree(S->d_W);
-    (void)hipFree(S->d_cum);
-    (void)hipFree(S->d_cumw);
+    (void)hipFree(S->d_cnt);
     (void)hipFree(S->d_blocks);
     (void)hipFree(S->d_coff);
     (void)hipFree(S->d_wcol);
@@ -349,35 +345,34 @@ int harvest_timing(fskmc_ctx* c)
     return FSKMC_OK;
 }
 
-// Start event of a timed launch, or -1 when this launch is not sampled.
-long timing_begin(fskmc_ctx* c)
+// Timing events for this launch (kernel-side start/stop), or none when the
+// launch is not sampled.
+LaunchTiming timing_begin(fskmc_ctx* c)
 {
+    LaunchTiming tm;
     if (c->timing_stride <= 0 || (c->launch_counter++ % (uint64_t)c->timing_stride) != 0)
-        return -1;
+        return tm;
     if (c->ev_used * 2 == c->ev_pool.size()) {
         if (c->ev_pool.size() >= 8192) {
             if (harvest_timing(c))
-                return -1;
+                return tm;
         } else {
             for (int k = 0; k < 256; ++k) {
                 hipEvent_t e;
                 if (hipEventCreate(&e) != hipSuccess)
-                    return -1;
+                    return tm;
                 c->ev_pool.push_back(e);
             }
         }
     }
-    const size_t i = c->ev_used;
-    if (hipEventRecord(c->ev_pool[2 * i], c->stream) != hipSuccess)
-        return -1;
-    return (long)i;
+    tm.start = c->ev_pool[2 * c->ev_used];
+    tm.stop = c->ev_pool[2 * c->ev_used + 1];
+    return tm;
 }
 
-void timing_end(fskmc_ctx* c, long i)
+void timing_end(fskmc_ctx* c, const LaunchTiming& tm)
 {
-    if (i < 0)
-        return;
-    if (hipEventRecord(c->ev_pool[2 * (size_t)i + 1], c->stream) == hipSuccess)
+    if (tm.start)
         c->ev_used++;
 }
 
@@ -385,9 +380,7 @@ int reset_counters(fskmc_sim* S)
 {
     hipStream_t st = S->ctx->stream;
     S->block_windows = 0;
-    HIP_TRY(launch_fill_u32(S->d_W, S->nb, 0u, st));
-    HIP_TRY(launch_fill_u64(S->d_cum, S->nb, 0ull, st));
-    HIP_TRY(launch_fill_u32(S->d_cumw, S->nb, 0u, st));
+    HIP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(S->d_cnt), 2 * (int64_t)S->nb, 0ull, st));
     return FSKMC_OK;
 }
 
@@ -397,9 +390,7 @@ int enqueue_window(fskmc_sim* S, uint64_t w)
     SweepArgs a;
     a.lat = S->d_lat;
     a.table = S->d_table;
-    a.W_last = S->d_W;
-    a.cum_events = S->d_cum;
-    a.cum_writes = S->d_cumw;
+    a.cnt = S->d_cnt;
     a.blocks = S->d_blocks + S->colour_off[c];
     a.n_blocks = S->colour_off[c + 1] - S->colour_off[c];
     a.Lx = S->lat.Lx;
@@ -409,8 +400,8 @@ int enqueue_window(fskmc_sim* S, uint64_t w)
     a.k1 = S->key.replica;
     a.w = (uint32_t)w;
     a.dur = S->win_dur[w];
-    const long tk = timing_begin(S->ctx);
-    HIP_TRY(launch_sweep_single(S->model, S->P, S->shape, S->ctx->wpg, a, S->ctx->stream));
+    const LaunchTiming tk = timing_begin(S->ctx);
+    HIP_TRY(launch_sweep_single(S->model, S->P, S->shape, S->ctx->wpg, a, S->ctx->stream, tk));
     timing_end(S->ctx, tk);
     S->block_windows += (uint64_t)a.n_blocks;
     return FSKMC_OK;
@@ -419,7 +410,7 @@ int enqueue_window(fskmc_sim* S, uint64_t w)
 size_t footprint_of(int64_t N, int model, int nb, uint64_t n_windows, int n_colours)
 {
     const size_t tab = model == FSKMC_MODEL_FLIP ? 10 * 8 : 243 * 14 * 8;
-    return (size_t)N + tab + (size_t)nb * (4 + 8 + 4 + 4) + (size_t)(n_colours + 1) * 4 +
+    return (size_t)N + tab + (size_t)nb * (sizeof(BlockCount) + 4) + (size_t)(n_colours + 1) * 4 +
            (size_t)n_windows * (1 + 8);
 }
 
@@ -628,8 +619,7 @@ int fskmc_sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, co
     (void)hipSetDevice(ctx->device);
     const int64_t N = n_sites(S->lat);
     if ((rc = dev_alloc(&S->d_lat, (size_t)N)) || (rc = dev_alloc(&S->d_table, S->table.size())) ||
-        (rc = dev_alloc(&S->d_W, S->nb)) || (rc = dev_alloc(&S->d_cum, S->nb)) ||
-        (rc = dev_alloc(&S->d_cumw, S->nb)) || (rc = dev_alloc(&S->d_blocks, S->blocks.size())) ||
+        (rc = dev_alloc(&S->d_cnt, S->nb)) || (rc = dev_alloc(&S->d_blocks, S->blocks.size())) ||
         (rc = dev_alloc(&S->d_coff, S->colour_off.size())) || (rc = dev_alloc(&S->d_wcol, S->n_windows)) ||
         (rc = dev_alloc(&S->d_wdur, S->n_windows))) {
         free_sim_device(S);
@@ -770,7 +760,7 @@ int fskmc_sim_observe(fskmc_sim* S, fskmc_obs* out)
         return fail(FSKMC_EINVAL, "NULL argument");
     fskmc_ctx* c = S->ctx;
     HIP_TRY(launch_fill_u64((uint64_t*)c->d_obs, 9, 0ull, c->stream));
-    HIP_TRY(launch_observe(S->d_lat, S->lat.Lx, S->lat.Ly, S->lat.dim, S->d_cum, S->d_cumw, S->nb, c->d_obs,
+    HIP_TRY(launch_observe(S->d_lat, S->lat.Lx, S->lat.Ly, S->lat.dim, S->d_cnt, S->nb, c->d_obs,
                            c->stream));
     HIP_TRY(hipMemcpyAsync(c->h_obs, c->d_obs, 9 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -799,8 +789,12 @@ int fskmc_sim_block_events(fskmc_sim* S, uint32_t* out, size_t n_blocks)
         return fail(FSKMC_EINVAL, "NULL argument");
     if (n_blocks != (size_t)S->nb)
         return fail(FSKMC_EINVAL, "sim has %d blocks, got %zu", S->nb, n_blocks);
-    HIP_TRY(hipMemcpyAsync(out, S->d_W, n_blocks * 4, hipMemcpyDeviceToHost, S->ctx->stream));
+    std::vector<BlockCount> rec(n_blocks);
+    HIP_TRY(hipMemcpyAsync(rec.data(), S->d_cnt, n_blocks * sizeof(BlockCount), hipMemcpyDeviceToHost,
+                           S->ctx->stream));
     HIP_TRY(hipStreamSynchronize(S->ctx->stream));
+    for (size_t i = 0; i < n_blocks; ++i)
+        out[i] = rec[i].W;
     return FSKMC_OK;
 }
 
@@ -936,9 +930,7 @@ int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t 
             JobDesc& d = hj[g.job_off + k];
             d.lat = S->d_lat;
             d.table = S->d_table;
-            d.W_last = S->d_W;
-            d.cum_events = S->d_cum;
-            d.cum_writes = S->d_cumw;
+            d.cnt = S->d_cnt;
             d.blocks = S->d_blocks;
             d.colour_off = S->d_coff;
             d.win_colour = S->d_wcol;
@@ -963,9 +955,9 @@ int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t 
     HIP_TRY(hipEventRecord(ctx->stage_free, ctx->stream));
     for (uint32_t step = 0; step < windows; ++step) {
         for (auto& g : groups) {
-            const long tk = timing_begin(ctx);
+            const LaunchTiming tk = timing_begin(ctx);
             HIP_TRY(launch_sweep_batched(g.model, g.P, g.shape, ctx->wpg, ctx->d_jobs + g.job_off,
-                                         ctx->d_items + g.item_off, g.items, step, ctx->stream));
+                                         ctx->d_items + g.item_off, g.items, step, ctx->stream, tk));
             timing_end(ctx, tk);
         }
     }

@@ -8,32 +8,24 @@ namespace fskmc {
 
 enum { MODEL_FLIP = 1, MODEL_ZGB = 2 };
 
-// Maximum sweep kernel variants: sites per lane P in {1,4,16}; square blocks
+// Sweep kernel variants: sites per lane P in {1,4,16}; square blocks
 // (8x8, 16x16, 32x32) or 1D rows (64P x 1).
 enum Shape { SHAPE_SQ = 0, SHAPE_ROW = 1 };
 
-// Everything one wave needs to run one block-window.
-struct BlockWork {
-    uint8_t* lat;           // lattice, y*Lx + x
-    const double* table;    // flip: 2(z+1) site rates; zgb: 243*14 channels+total
-    uint32_t* W_last;       // per block: accepted events in its last window
-    uint64_t* cum_events;   // per block: accepted events since reset
-    uint32_t* cum_writes;   // per block: windows that changed the block
-    int Lx, Ly;
-    int m;                  // block id (row-major over blocks)
-    int NBX;                // blocks per row
-    uint32_t k0, k1;        // Philox key
-    uint32_t w;             // window index (Philox counter word 2)
-    double dur;             // window duration
+// Per-block counters, one 16-byte record: accepted events in the block's
+// last window (the workload W of Sec. 6), windows that changed the block
+// (and were written back), and accepted events since the last reset.
+struct BlockCount {
+    uint32_t W;
+    uint32_t writes;
+    unsigned long long events;
 };
 
 // Kernel arguments of the single-simulation sweep (one colour, one window).
 struct SweepArgs {
     uint8_t* lat;
     const double* table;
-    uint32_t* W_last;
-    uint64_t* cum_events;
-    uint32_t* cum_writes;
+    BlockCount* cnt;
     const int32_t* blocks;  // block ids of the active colour
     int n_blocks;
     int Lx, Ly, NBX;
@@ -45,9 +37,7 @@ struct SweepArgs {
 struct JobDesc {
     uint8_t* lat;
     const double* table;
-    uint32_t* W_last;
-    uint64_t* cum_events;
-    uint32_t* cum_writes;
+    BlockCount* cnt;
     const int32_t* blocks;      // block ids grouped by colour
     const int32_t* colour_off;  // n_colours+1 offsets into blocks
     const int8_t* win_colour;   // per window
@@ -61,16 +51,23 @@ struct JobDesc {
     uint32_t pad;
 };
 
+// Optional kernel-side timing: when both events are set, the launch records
+// them at the kernel's own start and end (hipExtLaunchKernelGGL).
+struct LaunchTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // Launchers implemented in fskmc_kernels.hip.  They return hipError_t.
-hipError_t launch_sweep_single(int model, int P, int shape, int wpg, const SweepArgs& a, hipStream_t s);
+hipError_t launch_sweep_single(int model, int P, int shape, int wpg, const SweepArgs& a, hipStream_t s,
+                               LaunchTiming tm);
 hipError_t launch_sweep_batched(int model, int P, int shape, int wpg, const JobDesc* jobs,
                                 const uint32_t* item_job, uint32_t n_items, uint64_t step,
-                                hipStream_t s);
+                                hipStream_t s, LaunchTiming tm);
 hipError_t launch_init(uint8_t* lat, int64_t n, int kind, double p, uint32_t k0, uint32_t k1,
                        hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
-hipError_t launch_observe(const uint8_t* lat, int Lx, int Ly, int dim, const uint64_t* cum_events,
-                          const uint32_t* cum_writes, int n_blocks, unsigned long long* out9, hipStream_t s);
+hipError_t launch_observe(const uint8_t* lat, int Lx, int Ly, int dim, const BlockCount* cnt, int n_blocks,
+                          unsigned long long* out9, hipStream_t s);
 
 }  // namespace fskmc

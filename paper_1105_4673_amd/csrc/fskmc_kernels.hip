@@ -6,18 +6,21 @@
 // duration while all other sites stay frozen.  One wavefront owns one block:
 //
 //   * the block and its one-site halo are staged from HBM into a per-wave LDS
-//     tile (coalesced row segments of P bytes per lane);
+//     tile (row segments of P bytes per lane), with an XCD-aware block order
+//     so that blocks sharing cache lines are served by the same L2;
 //   * leaf rates come from the host-built FP64 table (a per-wave LDS copy)
 //     indexed by the site's neighbourhood;
-//   * the canonical heap sum tree over the b*b leaves (row-major leaf order,
-//     node = left + right) lives in VGPRs: each lane holds the pairwise tree
-//     of its P consecutive leaves, and the top six levels are an xor
-//     butterfly across the 64 lanes (a + b == b + a in IEEE, so every lane
-//     holds exactly the node values of the heap tree);
-//   * the descent is done by all lanes at once: lane j checks whether the
-//     root-to-leaf path of its own subtree is the one the serial descent
-//     takes, a ballot picks the single consistent lane, which finishes the
-//     last log2(P) levels in registers;
+//   * the canonical heap sum tree over the leaves (row-major leaf order,
+//     node = left + right) lives in registers: each lane holds the pairwise
+//     tree of its P consecutive leaves; the next four levels are a butterfly
+//     inside each 16-lane row built with DPP lane moves (quad_perm,
+//     row_half_mirror, row_mirror), and the two top levels are four uniform
+//     values read with readlane.  Since a + b == b + a in IEEE arithmetic,
+//     every lane holds exactly the node values of the heap tree;
+//   * the descent takes the two top levels uniformly, then all 16 lanes of
+//     the chosen row check at once whether the path of their own subtree is
+//     the one the serial descent takes; a ballot picks the single consistent
+//     lane, which finishes the last log2(P) levels in registers;
 //   * the Philox4x32-10 draws and their logarithms are computed 64 at a time,
 //     one per lane, and broadcast with readlane as events consume them.
 //
@@ -25,6 +28,8 @@
 // contraction (built with -ffp-contract=off), so the results match the CPU
 // statement of the scheme bit for bit.
 #include "fskmc_internal.h"
+
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 
@@ -125,6 +130,18 @@ __device__ __forceinline__ double uniform_f64(double v)
     return __longlong_as_double(((long long)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
+// Value of a double in another lane through a DPP lane move (CTRL is the
+// gfx9 DPP control: 0xB1 = quad_perm [1,0,3,2], 0x4E = quad_perm [2,3,0,1],
+// 0x141 = row_half_mirror, 0x140 = row_mirror).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 // A lane's run of P consecutive sites of one block row, as packed bytes.
 template <int P>
 struct Seg {
@@ -179,17 +196,82 @@ struct Cfg {
     static constexpr int S = BX + 2 * P;                 // tile row stride
     static constexpr int TILE = ((BY + 2) * S + 15) / 16 * 16;
     static constexpr int NTAB = MODEL == MODEL_FLIP ? 2 * (Z + 1) : 243;
-    static constexpr int LDS = TILE + NTAB * 8;          // bytes per wave
+    static constexpr int XFER = P == 16 ? 16 * 8 : 0;    // in-lane descent exchange
+    static constexpr int LDS = TILE + NTAB * 8 + XFER;   // bytes per wave
     static constexpr int LPR = BX / P;                   // lanes per row
     static constexpr int LOGP = P == 1 ? 0 : (P == 4 ? 2 : 4);
 };
 
-// Leaves of this lane from the LDS tile, then its in-lane pairwise tree and
-// the cross-lane butterfly: g[s] = sum of the aligned group of 2^s lanes that
-// contains this lane, pr[s] = that of the sibling group; g[6] = root.
+// The block's sum tree.  Per lane: lv = pairwise tree of its P leaves
+// (lv[1] lane sum, lv[P+q] leaf q); g[s] (s = 0..4) = sum of the aligned
+// group of 2^s lanes containing the lane, pr[s] (s = 0..3) = that of the
+// sibling group.  Uniform: q4[k] = sum of lanes [16k, 16k+16), h5[k] = sum of
+// lanes [32k, 32k+32), R = root.
+template <int P>
+struct Tree {
+    double lv[2 * P];
+    double g[5], pr[4];
+    double q4[4], h5[2], R;
+};
+
+// Butterfly inside each 16-lane row: from x (this lane's value) g[s] = sum of
+// the aligned 2^s-lane group, pr[s] = sum of its sibling group, s = 0..3, and
+// g[4] = the row's sum.  DPP moves pick any lane of the sibling group; all
+// lanes of a group hold the same bits because IEEE addition commutes.
+__device__ __forceinline__ void row_butterfly(double x, double (&g)[5], double (&pr)[4])
+{
+    g[0] = x;
+    pr[0] = dpp_f64<0xB1>(g[0]);
+    g[1] = g[0] + pr[0];
+    pr[1] = dpp_f64<0x4E>(g[1]);
+    g[2] = g[1] + pr[1];
+    pr[2] = dpp_f64<0x141>(g[2]);
+    g[3] = g[2] + pr[2];
+    pr[3] = dpp_f64<0x140>(g[3]);
+    g[4] = g[3] + pr[3];
+}
+
+// Four descent levels inside a 16-lane row whose subtree sums are (g, pr):
+// each lane follows its own root-to-leaf path and stays `ok` while every
+// decision agrees with its lane bits.  Returns the residual target.
+__device__ __forceinline__ double row_descend(const double (&g)[5], const double (&pr)[4], double tl, int lane,
+                                              bool& ok)
+{
+#pragma unroll
+    for (int s = 3; s >= 0; --s) {
+        const bool bit = (lane >> s) & 1;
+        const double left = bit ? pr[s] : g[s];
+        const double right = bit ? g[s] : pr[s];
+        const bool go_right = !(tl < left || right == 0.0);
+        ok = ok && (go_right == bit);
+        if (go_right)
+            tl = tl - left;
+    }
+    return tl;
+}
+
+// In-lane pairwise levels, the row butterfly and the two top levels, from
+// the leaves in T.lv[P..2P).
+template <int P>
+__device__ __forceinline__ void finish_tree(Tree<P>& T)
+{
+#pragma unroll
+    for (int k = P - 1; k >= 1; --k)
+        T.lv[k] = T.lv[2 * k] + T.lv[2 * k + 1];
+    row_butterfly(T.lv[1], T.g, T.pr);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        T.q4[k] = readlane_f64(T.g[4], 16 * k);
+    T.h5[0] = T.q4[0] + T.q4[1];
+    T.h5[1] = T.q4[2] + T.q4[3];
+    T.R = T.h5[0] + T.h5[1];
+}
+
+// Leaves from the LDS tile: the table entry of each site's neighbourhood
+// (spin flip: s*(z+1) + #occupied neighbours; reaction model: the pattern
+// s + 3E + 9W + 27N + 81S).
 template <int P, int BX, int BY, int MODEL>
-__device__ __forceinline__ void build_tree(const uint8_t* tile, int tb, const double* tab, double (&lv)[2 * P],
-                                           double (&g)[7], double (&pr)[6])
+__device__ __forceinline__ void build_tree(const uint8_t* tile, int tb, const double* tab, Tree<P>& T)
 {
     using C = Cfg<P, BX, BY, MODEL>;
     const Seg<P> o = load_seg<P>(tile + tb);
@@ -214,87 +296,185 @@ __device__ __forceinline__ void build_tree(const uint8_t* tile, int tb, const do
             idx = s * (C::Z + 1) + E + W + N + Sd;
         else
             idx = s + 3 * E + 9 * W + 27 * N + 81 * Sd;
-        lv[P + q] = tab[idx];
+        T.lv[P + q] = tab[idx];
+    }
+    finish_tree(T);
+}
+
+// Spin flip: a lane's site states and occupied-neighbour counts as packed
+// bytes, kept in registers for the whole window (the halo is frozen, so only
+// flips inside the block change them).
+template <int P>
+struct FlipSites {
+    uint32_t s[(P + 3) / 4], n[(P + 3) / 4];
+};
+
+template <int P, int BX, int BY>
+__device__ __forceinline__ void flip_sites_from_tile(const uint8_t* tile, int tb, FlipSites<P>& F)
+{
+    constexpr int S = BX + 2 * P;
+    constexpr int W = (P + 3) / 4;
+    const Seg<P> o = load_seg<P>(tile + tb);
+    const uint32_t lft = tile[tb - 1], rgt = tile[tb + P];
+    Seg<P> up, dn;
+    if constexpr (BY > 1) {
+        up = load_seg<P>(tile + tb + S);
+        dn = load_seg<P>(tile + tb - S);
     }
 #pragma unroll
-    for (int k = P - 1; k >= 1; --k)
-        lv[k] = lv[2 * k] + lv[2 * k + 1];
-    g[0] = lv[1];
-#pragma unroll
-    for (int s = 0; s < 6; ++s) {
-        pr[s] = __shfl_xor(g[s], 1 << s, 64);
-        g[s + 1] = g[s] + pr[s];
+    for (int k = 0; k < W; ++k) {
+        uint32_t Lw, Rw; // bytes of the -x and +x neighbours of each site
+        if constexpr (P == 1) {
+            Lw = lft;
+            Rw = rgt;
+        } else {
+            Lw = (o.w[k] << 8) | (k > 0 ? o.w[k - 1] >> 24 : lft);
+            Rw = (o.w[k] >> 8) | ((k + 1 < W ? (o.w[k + 1] & 0xffu) : rgt) << 24);
+        }
+        uint32_t n = Lw + Rw;
+        if constexpr (BY > 1)
+            n += up.w[k] + dn.w[k];
+        F.s[k] = o.w[k];
+        F.n[k] = n; // each byte <= 4: no carries between bytes
     }
 }
 
-// One block-window.  `lds` is this wave's private LDS slice.
+template <int P>
+__device__ __forceinline__ uint32_t byte_bit(int d)
+{
+    constexpr unsigned lim = P < 4 ? P : 4;
+    return (unsigned)d < lim ? 1u << (8 * d) : 0u;
+}
+
+// Flip of block site (xi, yi) to state v: toggle it and add +-1 to the counts
+// of its in-block neighbours.  Lane geometry: row r, columns c0 .. c0+P-1.
+template <int P>
+__device__ __forceinline__ void flip_apply(FlipSites<P>& F, int r, int c0, int xi, int yi, bool v)
+{
+    constexpr int W = (P + 3) / 4;
+    const int far = -1000;
+    const int p_self = r == yi ? xi - c0 : far;
+    const int p_l = r == yi ? xi - 1 - c0 : far;
+    const int p_r = r == yi ? xi + 1 - c0 : far;
+    const int p_v = (r == yi - 1 || r == yi + 1) ? xi - c0 : far;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const uint32_t sm = byte_bit<P>(p_self - 4 * k);
+        const uint32_t nm = byte_bit<P>(p_l - 4 * k) | byte_bit<P>(p_r - 4 * k) | byte_bit<P>(p_v - 4 * k);
+        F.s[k] ^= sm;
+        F.n[k] = v ? F.n[k] + nm : F.n[k] - nm;
+    }
+}
+
+template <int P, int Z>
+__device__ __forceinline__ void flip_leaves(const FlipSites<P>& F, const double* tab, Tree<P>& T)
+{
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const uint32_t s = (F.s[q >> 2] >> (8 * (q & 3))) & 0xffu;
+        const uint32_t n = (F.n[q >> 2] >> (8 * (q & 3))) & 0xffu;
+        T.lv[P + q] = tab[s * (Z + 1) + n];
+    }
+    finish_tree(T);
+}
+
+// Descent of the heap tree with target tg in [0, R): at each node go left
+// when tg < left or the right subtree is empty, else subtract left and go
+// right.  Returns the leaf index within the block; *tg_out = residual target.
+// xfer: 16 doubles of this wave's LDS, used when P == 16.
+template <int P>
+__device__ __forceinline__ int descend(const Tree<P>& T, double tg, int lane, double* tg_out, double* xfer)
+{
+    // two top levels, uniform
+    bool r = !(tg < T.h5[0] || T.h5[1] == 0.0);
+    if (r)
+        tg = tg - T.h5[0];
+    const int half = r ? 1 : 0;
+    const double L1 = half ? T.q4[2] : T.q4[0];
+    const double R1 = half ? T.q4[3] : T.q4[1];
+    r = !(tg < L1 || R1 == 0.0);
+    if (r)
+        tg = tg - L1;
+    const int quarter = 2 * half + (r ? 1 : 0);
+    // four levels inside the chosen 16-lane row
+    bool ok = (lane >> 4) == quarter;
+    double tl = row_descend(T.g, T.pr, tg, lane, ok);
+    int q = 0;
+    if constexpr (P == 4) {
+        // two levels inside the lane, in registers (constant indices only)
+        bool gr = !(tl < T.lv[2] || T.lv[3] == 0.0);
+        if (gr)
+            tl = tl - T.lv[2];
+        const double L = gr ? T.lv[6] : T.lv[4];
+        const double Rr = gr ? T.lv[7] : T.lv[5];
+        const bool gr2 = !(tl < L || Rr == 0.0);
+        if (gr2)
+            tl = tl - L;
+        q = 2 * (gr ? 1 : 0) + (gr2 ? 1 : 0);
+    }
+    const uint64_t bal = __ballot(ok);
+    const int js = (__ffsll((unsigned long long)bal) - 1) & 63;
+    if constexpr (P == 16) {
+        // the lane's 16 leaves go to lanes 0..15 through LDS, which rebuild
+        // the four in-lane levels with the same row butterfly and descend
+        const double tu = readlane_f64(tl, js);
+        if (lane == js) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                xfer[i] = T.lv[16 + i];
+        }
+        wave_sync();
+        double g2[5], pr2[4];
+        row_butterfly(xfer[lane & 15], g2, pr2);
+        bool ok2 = lane < 16;
+        const double t2 = row_descend(g2, pr2, tu, lane, ok2);
+        const uint64_t bal2 = __ballot(ok2);
+        q = (__ffsll((unsigned long long)bal2) - 1) & 15;
+        *tg_out = readlane_f64(t2, q);
+        wave_sync();
+        return js * P + q;
+    } else {
+        q = __builtin_amdgcn_readlane(q, js) & (P - 1);
+        *tg_out = readlane_f64(tl, js);
+        return js * P + q;
+    }
+}
+
+// The serial SSA kernel of one block for one window (Sec. 1, eqs. totalrate
+// and skeleton) on the block's LDS tile.  Draw e uses Philox counter
+// (e, m, w, 0); the draw whose time passes the window end is discarded.
+// Spin flip keeps the block in registers during the window and puts it back
+// into the tile at the end; pair events update the tile in place.
+// Returns the number of accepted events.
 template <int P, int BX, int BY, int MODEL>
-__device__ void block_window(const BlockWork& bw, uint8_t* lds)
+__device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const double* __restrict__ chan, uint32_t m,
+                                               uint32_t w, double dur, uint32_t k0, uint32_t k1)
 {
     using C = Cfg<P, BX, BY, MODEL>;
     const int lane = threadIdx.x & 63;
-    uint8_t* tile = lds;
-    double* tab = reinterpret_cast<double*>(lds + C::TILE);
-
-    // rate table into LDS (flip: site rates; reaction model: site totals)
-    for (int i = lane; i < C::NTAB; i += 64)
-        tab[i] = (MODEL == MODEL_FLIP) ? bw.table[i] : bw.table[i * 14 + 13];
-
-    // stage the block and its halo
-    const int bi = bw.m % bw.NBX, bj = bw.m / bw.NBX;
-    const int x0 = bi * BX, y0 = bj * BY;
     const int r = lane / C::LPR, c0 = (lane % C::LPR) * P;
-    const int gy = y0 + r, gx = x0 + c0;
-    const size_t Lx = (size_t)bw.Lx;
-    uint8_t* grow = bw.lat + (size_t)gy * Lx;
     const int tb = (r + 1) * C::S + P + c0;
-    const bool has_top = C::DIM == 2 && r == 0;
-    const bool has_bot = C::DIM == 2 && r == BY - 1;
-    const bool has_l = c0 == 0, has_r = c0 + P == BX;
-    const int xl = (x0 == 0 ? bw.Lx : x0) - 1;
-    const int xr = (x0 + BX == bw.Lx) ? 0 : x0 + BX;
-    uint8_t* gtop = bw.lat + (size_t)(gy == 0 ? bw.Ly - 1 : gy - 1) * Lx + gx;
-    uint8_t* gbot = bw.lat + (size_t)(gy + 1 == bw.Ly ? 0 : gy + 1) * Lx + gx;
-    {
-        const Seg<P> own = load_seg<P>(grow + gx);
-        Seg<P> top, bot;
-        uint32_t lb = 0, rb = 0;
-        if (has_top)
-            top = load_seg<P>(gtop);
-        if (has_bot)
-            bot = load_seg<P>(gbot);
-        if (has_l)
-            lb = grow[xl];
-        if (has_r)
-            rb = grow[xr];
-        store_seg<P>(tile + tb, own);
-        if (has_top)
-            store_seg<P>(tile + tb - C::S, top);
-        if (has_bot)
-            store_seg<P>(tile + tb + C::S, bot);
-        if (has_l)
-            tile[tb - 1] = (uint8_t)lb;
-        if (has_r)
-            tile[tb + P] = (uint8_t)rb;
+    Tree<P> T;
+    FlipSites<P> F;
+    if constexpr (MODEL == MODEL_FLIP) {
+        flip_sites_from_tile<P, BX, BY>(tile, tb, F);
+        flip_leaves<P, C::Z>(F, tab, T);
+    } else {
+        build_tree<P, BX, BY, MODEL>(tile, tb, tab, T);
     }
-    wave_sync();
-
-    double lv[2 * P], g[7], pr[6];
-    build_tree<P, BX, BY, MODEL>(tile, tb, tab, lv, g, pr);
 
     double t = 0.0;
-    uint32_t e = 0;
-    uint32_t e0 = 0;
+    uint32_t e = 0, e0 = 0;
     double nl_b = 0.0, v_b = 0.0; // this lane's draw e0 + lane: -log U and V
     bool have_batch = false;
     for (;;) {
-        const double R = uniform_f64(g[6]);
+        const double R = uniform_f64(T.R);
         if (R == 0.0)
             break;
         if (!have_batch || e - e0 >= 64u) {
             e0 = have_batch ? e : 0u;
             have_batch = true;
-            const uint4 rr = philox10(make_uint4(e0 + (uint32_t)lane, (uint32_t)bw.m, bw.w, 0u), bw.k0, bw.k1);
+            const uint4 rr = philox10(make_uint4(e0 + (uint32_t)lane, m, w, 0u), k0, k1);
             nl_b = -fs_log(unif_open0(rr));
             v_b = unif_open1(rr);
         }
@@ -302,57 +482,29 @@ __device__ void block_window(const BlockWork& bw, uint8_t* lds)
         const double nl = readlane_f64(nl_b, k);
         const double V = readlane_f64(v_b, k);
         const double tn = t + nl / R;
-        if (!(tn < bw.dur))
+        if (!(tn < dur))
             break;
         t = tn;
-
-        // descent, top six levels: is this lane's subtree on the path?
-        double tl = V * R;
-        bool ok = true;
-#pragma unroll
-        for (int s = 5; s >= 0; --s) {
-            const bool bit = (lane >> s) & 1;
-            const double left = bit ? pr[s] : g[s];
-            const double right = bit ? g[s] : pr[s];
-            const bool go_right = !(tl < left || right == 0.0);
-            ok = ok && (go_right == bit);
-            if (go_right)
-                tl = tl - left;
-        }
-        // the remaining log2(P) levels inside the lane
-        int kk = 1;
-#pragma unroll
-        for (int lev = 0; lev < C::LOGP; ++lev) {
-            const int width = 1 << lev;
-            double L = lv[2 * width], Rr = lv[2 * width + 1];
-#pragma unroll
-            for (int c = 1; c < width; ++c) {
-                if (kk - width == c) {
-                    L = lv[2 * (width + c)];
-                    Rr = lv[2 * (width + c) + 1];
-                }
-            }
-            const bool go_right = !(tl < L || Rr == 0.0);
-            if (go_right)
-                tl = tl - L;
-            kk = 2 * kk + (go_right ? 1 : 0);
-        }
-        const uint64_t bal = __ballot(ok);
-        const int js = __ffsll((unsigned long long)bal) - 1;
-        const int q = __builtin_amdgcn_readlane(kk - P, js);
-        const int leaf = js * P + q;
+        double tg;
+        const int leaf = descend<P>(T, V * R, lane, &tg, tab + C::NTAB);
         const int lx = leaf % BX, ly = leaf / BX;
-        const int ts = (ly + 1) * C::S + P + lx;
-
         if constexpr (MODEL == MODEL_FLIP) {
-            if (lane == 0)
-                tile[ts] = (uint8_t)(tile[ts] ^ 1u);
+            const int js = leaf / P, q = leaf % P;
+            uint32_t word = 0;
+#pragma unroll
+            for (int kw = 0; kw < (P + 3) / 4; ++kw) {
+                const uint32_t wv = (uint32_t)__builtin_amdgcn_readlane((int)F.s[kw], js);
+                word = (q >> 2) == kw ? wv : word;
+            }
+            const bool was = (word >> (8 * (q & 3))) & 1u;
+            flip_apply<P>(F, r, c0, lx, ly, !was);
+            flip_leaves<P, C::Z>(F, tab, T);
         } else {
-            double tg = readlane_f64(tl, js);
+            const int ts = (ly + 1) * C::S + P + lx;
             const uint32_t s = tile[ts];
             const uint32_t nE = tile[ts + 1], nW = tile[ts - 1], nN = tile[ts + C::S], nS = tile[ts - C::S];
-            const int pat = (int)(s + 3 * nE + 9 * nW + 27 * nN + 81 * nS);
-            const double* ch = bw.table + pat * 14;
+            const int pat = __builtin_amdgcn_readfirstlane((int)(s + 3 * nE + 9 * nW + 27 * nN + 81 * nS));
+            const double* ch = chan + pat * 14;
             int pick = -1, last = -1;
             for (int c = 0; c < 13; ++c) {
                 const double rc = ch[c];
@@ -385,15 +537,81 @@ __device__ void block_window(const BlockWork& bw, uint8_t* lds)
                     }
                 }
             }
+            wave_sync();
+            build_tree<P, BX, BY, MODEL>(tile, tb, tab, T);
         }
-        wave_sync();
-        build_tree<P, BX, BY, MODEL>(tile, tb, tab, lv, g, pr);
         ++e;
         if (e == 0xFFFFFFFFu)
             break; // the draw counter is 32-bit; a window never gets here in practice
     }
+    if constexpr (MODEL == MODEL_FLIP) {
+        if (e > 0) {
+            Seg<P> o;
+#pragma unroll
+            for (int k = 0; k < (P + 3) / 4; ++k)
+                o.w[k] = F.s[k];
+            store_seg<P>(tile + tb, o);
+            wave_sync();
+        }
+    }
+    return e;
+}
 
-    // write back: the block (spin flip), the block and its halo (pair model)
+// One block-window of the streaming sweep: stage block + halo from the
+// lattice into LDS, run the SSA window, write back what may have changed
+// (the block for spin flip; block and halo for pair events), update counters.
+template <int P, int BX, int BY, int MODEL>
+__device__ __forceinline__ void block_window(uint8_t* __restrict__ lat, const double* __restrict__ table, BlockCount* cnt, int Lx,
+                             int Ly, int m, int NBX, uint32_t k0, uint32_t k1, uint32_t w, double dur, uint8_t* lds)
+{
+    using C = Cfg<P, BX, BY, MODEL>;
+    const int lane = threadIdx.x & 63;
+    uint8_t* tile = lds;
+    double* tab = reinterpret_cast<double*>(lds + C::TILE);
+
+    for (int i = lane; i < C::NTAB; i += 64)
+        tab[i] = (MODEL == MODEL_FLIP) ? table[i] : table[i * 14 + 13];
+
+    const int bi = m % NBX, bj = m / NBX;
+    const int x0 = bi * BX, y0 = bj * BY;
+    const int r = lane / C::LPR, c0 = (lane % C::LPR) * P;
+    const int gy = y0 + r, gx = x0 + c0;
+    const size_t sLx = (size_t)Lx;
+    uint8_t* grow = lat + (size_t)gy * sLx;
+    const int tb = (r + 1) * C::S + P + c0;
+    const bool has_top = C::DIM == 2 && r == 0;
+    const bool has_bot = C::DIM == 2 && r == BY - 1;
+    const bool has_l = c0 == 0, has_r = c0 + P == BX;
+    const int xl = (x0 == 0 ? Lx : x0) - 1;
+    const int xr = (x0 + BX == Lx) ? 0 : x0 + BX;
+    uint8_t* gtop = lat + (size_t)(gy == 0 ? Ly - 1 : gy - 1) * sLx + gx;
+    uint8_t* gbot = lat + (size_t)(gy + 1 == Ly ? 0 : gy + 1) * sLx + gx;
+    {
+        const Seg<P> own = load_seg<P>(grow + gx);
+        Seg<P> top, bot;
+        uint32_t lb = 0, rb = 0;
+        if (has_top)
+            top = load_seg<P>(gtop);
+        if (has_bot)
+            bot = load_seg<P>(gbot);
+        if (has_l)
+            lb = grow[xl];
+        if (has_r)
+            rb = grow[xr];
+        store_seg<P>(tile + tb, own);
+        if (has_top)
+            store_seg<P>(tile + tb - C::S, top);
+        if (has_bot)
+            store_seg<P>(tile + tb + C::S, bot);
+        if (has_l)
+            tile[tb - 1] = (uint8_t)lb;
+        if (has_r)
+            tile[tb + P] = (uint8_t)rb;
+    }
+    wave_sync();
+
+    const uint32_t e = ssa_window<P, BX, BY, MODEL>(tile, tab, table, (uint32_t)m, w, dur, k0, k1);
+
     if (e > 0) {
         store_seg<P>(grow + gx, load_seg<P>(tile + tb));
         if constexpr (MODEL == MODEL_ZGB) {
@@ -408,10 +626,20 @@ __device__ void block_window(const BlockWork& bw, uint8_t* lds)
         }
     }
     if (lane == 0) {
-        bw.W_last[bw.m] = e;
-        bw.cum_events[bw.m] += e;
-        bw.cum_writes[bw.m] += (e > 0) ? 1u : 0u;
+        cnt[m].W = e;
+        if (e > 0) {
+            atomicAdd(&cnt[m].writes, 1u);
+            atomicAdd(&cnt[m].events, (unsigned long long)e);
+        }
     }
+}
+
+// Workgroups are dispatched round-robin over the eight XCDs (L2 domains);
+// give each XCD a contiguous range of work so neighbouring blocks, which
+// share cache lines, are fetched by one L2.
+__device__ __forceinline__ uint32_t xcd_order(uint32_t wg, uint32_t G)
+{
+    return (G & 7u) ? wg : (wg & 7u) * (G >> 3) + (wg >> 3);
 }
 
 template <int P, int BX, int BY, int MODEL, int WPG>
@@ -420,24 +648,11 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_single(SweepArgs a)
     using C = Cfg<P, BX, BY, MODEL>;
     __shared__ __attribute__((aligned(16))) uint8_t lds[WPG * C::LDS];
     const int wid = threadIdx.x >> 6;
-    const int item = blockIdx.x * WPG + wid;
+    const int item = (int)xcd_order(blockIdx.x, gridDim.x) * WPG + wid;
     if (item >= a.n_blocks)
         return; // the whole wave leaves; waves never synchronise with each other
-    BlockWork bw;
-    bw.lat = a.lat;
-    bw.table = a.table;
-    bw.W_last = a.W_last;
-    bw.cum_events = a.cum_events;
-    bw.cum_writes = a.cum_writes;
-    bw.Lx = a.Lx;
-    bw.Ly = a.Ly;
-    bw.m = a.blocks[item];
-    bw.NBX = a.NBX;
-    bw.k0 = a.k0;
-    bw.k1 = a.k1;
-    bw.w = a.w;
-    bw.dur = a.dur;
-    block_window<P, BX, BY, MODEL>(bw, lds + wid * C::LDS);
+    block_window<P, BX, BY, MODEL>(a.lat, a.table, a.cnt, a.Lx, a.Ly, a.blocks[item], a.NBX, a.k0, a.k1, a.w,
+                                   a.dur, lds + wid * C::LDS);
 }
 
 template <int P, int BX, int BY, int MODEL, int WPG>
@@ -448,7 +663,7 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_batched(const JobDesc* __res
     using C = Cfg<P, BX, BY, MODEL>;
     __shared__ __attribute__((aligned(16))) uint8_t lds[WPG * C::LDS];
     const int wid = threadIdx.x >> 6;
-    const uint32_t item = blockIdx.x * WPG + wid;
+    const uint32_t item = xcd_order(blockIdx.x, gridDim.x) * WPG + wid;
     if (item >= n_items)
         return;
     const uint32_t j = item_job[item];
@@ -461,21 +676,8 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_batched(const JobDesc* __res
     const int beg = jd.colour_off[c], end = jd.colour_off[c + 1];
     if (k >= (uint32_t)(end - beg))
         return;
-    BlockWork bw;
-    bw.lat = jd.lat;
-    bw.table = jd.table;
-    bw.W_last = jd.W_last;
-    bw.cum_events = jd.cum_events;
-    bw.cum_writes = jd.cum_writes;
-    bw.Lx = jd.Lx;
-    bw.Ly = jd.Ly;
-    bw.m = jd.blocks[beg + k];
-    bw.NBX = jd.NBX;
-    bw.k0 = jd.k0;
-    bw.k1 = jd.k1;
-    bw.w = (uint32_t)w;
-    bw.dur = jd.win_dur[w];
-    block_window<P, BX, BY, MODEL>(bw, lds + wid * C::LDS);
+    block_window<P, BX, BY, MODEL>(jd.lat, jd.table, jd.cnt, jd.Lx, jd.Ly, jd.blocks[beg + k], jd.NBX, jd.k0,
+                                   jd.k1, (uint32_t)w, jd.win_dur[w], lds + wid * C::LDS);
 }
 
 // ---------------------------------------------------------------------------
@@ -509,8 +711,7 @@ __global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v)
 // per-block event and write-back counters.  Each thread takes four
 // consecutive sites.
 __global__ void k_observe(const uint8_t* __restrict__ lat, int Lx, int Ly, int dim,
-                          const uint64_t* __restrict__ cum_events, const uint32_t* __restrict__ cum_writes,
-                          int n_blocks, unsigned long long* out)
+                          const BlockCount* __restrict__ cnt, int n_blocks, unsigned long long* out)
 {
     unsigned long long acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t nq = (int64_t)Lx * Ly / 4;
@@ -538,8 +739,8 @@ __global__ void k_observe(const uint8_t* __restrict__ lat, int Lx, int Ly, int d
         }
     }
     for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < n_blocks; b += stride) {
-        acc[7] += cum_events[b];
-        acc[8] += cum_writes[b];
+        acc[7] += cnt[b].events;
+        acc[8] += cnt[b].writes;
     }
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
@@ -553,77 +754,81 @@ __global__ void k_observe(const uint8_t* __restrict__ lat, int Lx, int Ly, int d
 
 // ---------------------------------------------------------------------------
 // Dispatch.
+template <typename K, typename... Args>
+static hipError_t launch(K kernel, dim3 grid, dim3 block, hipStream_t s, LaunchTiming tm, Args... args)
+{
+    if (tm.start && tm.stop)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, tm.start, tm.stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+    return hipGetLastError();
+}
+
 template <int MODEL, int WPG>
-static hipError_t sweep_single_dispatch(int P, int shape, const SweepArgs& a, hipStream_t s)
+static hipError_t sweep_single_dispatch(int P, int shape, const SweepArgs& a, hipStream_t s, LaunchTiming tm)
 {
     const dim3 grid((a.n_blocks + WPG - 1) / WPG), block(64 * WPG);
     if (shape == SHAPE_SQ) {
         if (P == 1)
-            hipLaunchKernelGGL((k_sweep_single<1, 8, 8, MODEL, WPG>), grid, block, 0, s, a);
-        else if (P == 4)
-            hipLaunchKernelGGL((k_sweep_single<4, 16, 16, MODEL, WPG>), grid, block, 0, s, a);
-        else if (P == 16)
-            hipLaunchKernelGGL((k_sweep_single<16, 32, 32, MODEL, WPG>), grid, block, 0, s, a);
-        else
-            return hipErrorInvalidValue;
-    } else {
-        if constexpr (MODEL != MODEL_FLIP) {
-            return hipErrorInvalidValue;
-        } else {
-            if (P == 1)
-                hipLaunchKernelGGL((k_sweep_single<1, 64, 1, MODEL, WPG>), grid, block, 0, s, a);
-            else if (P == 4)
-                hipLaunchKernelGGL((k_sweep_single<4, 256, 1, MODEL, WPG>), grid, block, 0, s, a);
-            else if (P == 16)
-                hipLaunchKernelGGL((k_sweep_single<16, 1024, 1, MODEL, WPG>), grid, block, 0, s, a);
-            else
-                return hipErrorInvalidValue;
-        }
+            return launch(k_sweep_single<1, 8, 8, MODEL, WPG>, grid, block, s, tm, a);
+        if (P == 4)
+            return launch(k_sweep_single<4, 16, 16, MODEL, WPG>, grid, block, s, tm, a);
+        if (P == 16)
+            return launch(k_sweep_single<16, 32, 32, MODEL, WPG>, grid, block, s, tm, a);
+        return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+    if constexpr (MODEL != MODEL_FLIP) {
+        return hipErrorInvalidValue;
+    } else {
+        if (P == 1)
+            return launch(k_sweep_single<1, 64, 1, MODEL, WPG>, grid, block, s, tm, a);
+        if (P == 4)
+            return launch(k_sweep_single<4, 256, 1, MODEL, WPG>, grid, block, s, tm, a);
+        if (P == 16)
+            return launch(k_sweep_single<16, 1024, 1, MODEL, WPG>, grid, block, s, tm, a);
+        return hipErrorInvalidValue;
+    }
 }
 
 template <int MODEL, int WPG>
 static hipError_t sweep_batched_dispatch(int P, int shape, const JobDesc* jobs, const uint32_t* item_job,
-                                         uint32_t n_items, uint64_t step, hipStream_t s)
+                                         uint32_t n_items, uint64_t step, hipStream_t s, LaunchTiming tm)
 {
     const dim3 grid((n_items + WPG - 1) / WPG), block(64 * WPG);
     if (shape == SHAPE_SQ) {
         if (P == 1)
-            hipLaunchKernelGGL((k_sweep_batched<1, 8, 8, MODEL, WPG>), grid, block, 0, s, jobs, item_job, n_items, step);
-        else if (P == 4)
-            hipLaunchKernelGGL((k_sweep_batched<4, 16, 16, MODEL, WPG>), grid, block, 0, s, jobs, item_job, n_items, step);
-        else if (P == 16)
-            hipLaunchKernelGGL((k_sweep_batched<16, 32, 32, MODEL, WPG>), grid, block, 0, s, jobs, item_job, n_items, step);
-        else
-            return hipErrorInvalidValue;
-    } else {
-        if constexpr (MODEL != MODEL_FLIP) {
-            return hipErrorInvalidValue;
-        } else {
-            if (P == 1)
-                hipLaunchKernelGGL((k_sweep_batched<1, 64, 1, MODEL, WPG>), grid, block, 0, s, jobs, item_job, n_items, step);
-            else if (P == 4)
-                hipLaunchKernelGGL((k_sweep_batched<4, 256, 1, MODEL, WPG>), grid, block, 0, s, jobs, item_job, n_items, step);
-            else if (P == 16)
-                hipLaunchKernelGGL((k_sweep_batched<16, 1024, 1, MODEL, WPG>), grid, block, 0, s, jobs, item_job, n_items, step);
-            else
-                return hipErrorInvalidValue;
-        }
+            return launch(k_sweep_batched<1, 8, 8, MODEL, WPG>, grid, block, s, tm, jobs, item_job, n_items, step);
+        if (P == 4)
+            return launch(k_sweep_batched<4, 16, 16, MODEL, WPG>, grid, block, s, tm, jobs, item_job, n_items, step);
+        if (P == 16)
+            return launch(k_sweep_batched<16, 32, 32, MODEL, WPG>, grid, block, s, tm, jobs, item_job, n_items, step);
+        return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+    if constexpr (MODEL != MODEL_FLIP) {
+        return hipErrorInvalidValue;
+    } else {
+        if (P == 1)
+            return launch(k_sweep_batched<1, 64, 1, MODEL, WPG>, grid, block, s, tm, jobs, item_job, n_items, step);
+        if (P == 4)
+            return launch(k_sweep_batched<4, 256, 1, MODEL, WPG>, grid, block, s, tm, jobs, item_job, n_items, step);
+        if (P == 16)
+            return launch(k_sweep_batched<16, 1024, 1, MODEL, WPG>, grid, block, s, tm, jobs, item_job, n_items,
+                          step);
+        return hipErrorInvalidValue;
+    }
 }
 
-hipError_t launch_sweep_single(int model, int P, int shape, int wpg, const SweepArgs& a, hipStream_t s)
+hipError_t launch_sweep_single(int model, int P, int shape, int wpg, const SweepArgs& a, hipStream_t s,
+                               LaunchTiming tm)
 {
     if (a.n_blocks <= 0)
         return hipSuccess;
 #define FSKMC_SW(MOD)                                                          \
     switch (wpg) {                                                             \
-    case 1: return sweep_single_dispatch<MOD, 1>(P, shape, a, s);              \
-    case 2: return sweep_single_dispatch<MOD, 2>(P, shape, a, s);              \
-    case 4: return sweep_single_dispatch<MOD, 4>(P, shape, a, s);              \
-    case 8: return sweep_single_dispatch<MOD, 8>(P, shape, a, s);              \
+    case 1: return sweep_single_dispatch<MOD, 1>(P, shape, a, s, tm);          \
+    case 2: return sweep_single_dispatch<MOD, 2>(P, shape, a, s, tm);          \
+    case 4: return sweep_single_dispatch<MOD, 4>(P, shape, a, s, tm);          \
+    case 8: return sweep_single_dispatch<MOD, 8>(P, shape, a, s, tm);          \
     default: return hipErrorInvalidValue;                                      \
     }
     if (model == MODEL_FLIP) {
@@ -635,17 +840,17 @@ hipError_t launch_sweep_single(int model, int P, int shape, int wpg, const Sweep
 }
 
 hipError_t launch_sweep_batched(int model, int P, int shape, int wpg, const JobDesc* jobs, const uint32_t* item_job,
-                                uint32_t n_items, uint64_t step, hipStream_t s)
+                                uint32_t n_items, uint64_t step, hipStream_t s, LaunchTiming tm)
 {
     if (n_items == 0)
         return hipSuccess;
-#define FSKMC_SW(MOD)                                                                        \
-    switch (wpg) {                                                                           \
-    case 1: return sweep_batched_dispatch<MOD, 1>(P, shape, jobs, item_job, n_items, step, s); \
-    case 2: return sweep_batched_dispatch<MOD, 2>(P, shape, jobs, item_job, n_items, step, s); \
-    case 4: return sweep_batched_dispatch<MOD, 4>(P, shape, jobs, item_job, n_items, step, s); \
-    case 8: return sweep_batched_dispatch<MOD, 8>(P, shape, jobs, item_job, n_items, step, s); \
-    default: return hipErrorInvalidValue;                                                    \
+#define FSKMC_SW(MOD)                                                                            \
+    switch (wpg) {                                                                               \
+    case 1: return sweep_batched_dispatch<MOD, 1>(P, shape, jobs, item_job, n_items, step, s, tm); \
+    case 2: return sweep_batched_dispatch<MOD, 2>(P, shape, jobs, item_job, n_items, step, s, tm); \
+    case 4: return sweep_batched_dispatch<MOD, 4>(P, shape, jobs, item_job, n_items, step, s, tm); \
+    case 8: return sweep_batched_dispatch<MOD, 8>(P, shape, jobs, item_job, n_items, step, s, tm); \
+    default: return hipErrorInvalidValue;                                                        \
     }
     if (model == MODEL_FLIP) {
         FSKMC_SW(MODEL_FLIP)
@@ -687,12 +892,14 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_observe(const uint8_t* lat, int Lx, int Ly, int dim, const uint64_t* cum_events,
-                          const uint32_t* cum_writes, int n_blocks, unsigned long long* out9, hipStream_t s)
+hipError_t launch_observe(const uint8_t* lat, int Lx, int Ly, int dim, const BlockCount* cnt, int n_blocks,
+                          unsigned long long* out9, hipStream_t s)
 {
     const int64_t work = std::max<int64_t>((int64_t)Lx * Ly / 4, n_blocks);
-    hipLaunchKernelGGL(k_observe, dim3(grid_for(work, 256) > 2048 ? 2048 : grid_for(work, 256)), dim3(256), 0, s,
-                       lat, Lx, Ly, dim, cum_events, cum_writes, n_blocks, out9);
+    unsigned g = grid_for(work, 256);
+    if (g > 2048)
+        g = 2048;
+    hipLaunchKernelGGL(k_observe, dim3(g), dim3(256), 0, s, lat, Lx, Ly, dim, cnt, n_blocks, out9);
     return hipGetLastError();
 }
 
