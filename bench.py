@@ -5,19 +5,28 @@ Metric: KMC events per second (accepted lattice updates) on one GPU, at
 bit-exact agreement with the CPU oracle (the parity tests check the same
 kernels and launch configuration).
 
-Timed step (default workload): one whole run of the 1024^2 Ising-type lattice
-(spin flip, Arrhenius rates, J=1, h=0, beta=1, 16x16 blocks, 2 colours, Lie
-dt=0.1, T=100 = 2000 windows) from a Bernoulli(1/2) start: init kernel, every
-window's sweep launch, and the final observables.  Each step uses its own
-Philox replica key.  The lattice and all tables are resident in HBM before the
-timed region starts.
+Headline (value): one timed step = one whole run of the 1024^2 Ising-type
+lattice (spin flip, Arrhenius rates, J=1, h=0, beta=1, 16x16 blocks, 2 colours,
+Lie dt=0.1, T=100 = 2000 windows) from a Bernoulli(1/2) start: the init kernel,
+every window's sweep launch and the final observables.  Each step uses its own
+Philox replica key.  Lattices and tables are resident in HBM before the timed
+region starts.
 
-The JSON line also carries:
+Also in the JSON line:
   roofline      the sweep kernel's algorithmic HBM bytes per launch over its
-                average launch duration (HIP events on the launch stream, a
-                sample of the timed launches), against the 8 TB/s HBM peak;
+                average launch duration (kernel-side HIP events on the launch
+                stream, every k-th timed launch), against the 8 TB/s HBM peak;
   cpu_baseline  the oracle (plain single-threaded C, the blockwise scheme) on
-                a bounded sample of the same workload, on this host.
+                a bounded sample of the same workload, on this host;
+  batched       512 independent Ising replicas of mixed sizes (edges
+                128..1024) packed into one launch per window, against the same
+                512 runs advanced one after another, bit-identity checked;
+  served        Poisson request streams (50, 200, 1000 jobs/s) of mixed Ising
+                and A/B reaction jobs (edges log-uniform in [64, 2048], T in
+                [10, 200]) served with continuous batching: p50/p99
+                time-to-result and aggregate events/s;
+  sweep         events/s of the other (J, dt, split) points of the 1024^2
+                workload (fewer steps).
 """
 import argparse
 import json
@@ -38,24 +47,66 @@ def log(msg):
 
 def hbm_bytes(kind, b, block_windows, writes):
     """Algorithmic HBM bytes of the sweep: per block-window the block and its
-    one-site halo are read (b^2 + 4b bytes); a block that changed is written
-    back (b^2 bytes; the pair model also writes its halo); the block's event
-    counters are updated (4 + 2*8 + 2*4 bytes)."""
+    one-site halo are read (b^2 + 4b bytes) and its 16-byte counter record is
+    updated (28 bytes moved: W written, two counters read and written); a block
+    that changed is written back (b^2 bytes; the pair model also writes its
+    halo, b^2 + 4b)."""
     rd = b * b + 4 * b
     wr = b * b if kind == "flip" else b * b + 4 * b
     return block_windows * (rd + 28) + writes * wr
 
 
-def make_sim(F, ctx, wl, replica):
-    s = F.Sim(ctx, wl["kind"], wl["Lx"], wl["Ly"], wl["params"], b=wl["b"], n_colours=wl["n_colours"],
-              dt=wl["dt"], T=wl["T"], split=wl["split"], seed=wl.get("seed", 0), replica=replica)
-    return s
+def make_sim(F, ctx, wl, replica=None):
+    return F.Sim(ctx, wl["kind"], wl["Lx"], wl["Ly"], wl["params"], b=wl["b"], n_colours=wl["n_colours"],
+                 dt=wl["dt"], T=wl["T"], split=wl["split"], seed=wl.get("seed", 0),
+                 replica=wl.get("replica", 0) if replica is None else replica)
+
+
+def init_sim(sim, wl):
+    sim.init(1 if wl["init"] == "bernoulli" else 0, 0.5)
 
 
 def run_once(F, sim, wl):
-    sim.init(1 if wl["init"] == "bernoulli" else 0, 0.5)
+    init_sim(sim, wl)
     sim.run_to_end()
     return sim.observe()
+
+
+def roofline(F, ctx, kind, b, obs_list, launches, kernel_name):
+    """Achieved algorithmic HBM GB/s of the sweep kernel: bytes per launch
+    (from the run's block-window and write-back counts) over the average
+    duration of the launches bracketed by kernel-side timing events."""
+    ms_total, n_timed = F.fskmc_ctx_read_kernel_timing(ctx)
+    bw = sum(o["block_windows"] for o in obs_list)
+    wr = sum(o["writes"] for o in obs_list)
+    bytes_per_launch = hbm_bytes(kind, b, bw, wr) / max(launches, 1)
+    avg = ms_total / 1e3 / max(n_timed, 1)
+    achieved = bytes_per_launch / avg / 1e9 if n_timed else 0.0
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel_name,
+            "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg * 1e6, "timed_launches": n_timed}
+
+
+def bench_plain(F, ctx, wl, steps, warmup, stride):
+    sims = [make_sim(F, ctx, wl, replica=i) for i in range(warmup + steps)]
+    for i in range(warmup):
+        run_once(F, sims[i], wl)
+    F.fskmc_sync(ctx)
+    F.fskmc_ctx_read_kernel_timing(ctx)  # discard
+    F.fskmc_ctx_set_kernel_timing(ctx, stride)
+    F.fskmc_sync(ctx)
+    t0 = time.perf_counter()
+    obs = [run_once(F, sims[warmup + i], wl) for i in range(steps)]
+    F.fskmc_sync(ctx)
+    el = time.perf_counter() - t0
+    rl = roofline(F, ctx, wl["kind"], wl["b"], obs, sum(o["window"] for o in obs),
+                  f"k_sweep_single<P={wl['b'] ** 2 // 64},{wl['kind']}>")
+    F.fskmc_ctx_set_kernel_timing(ctx, 0)
+    for s in sims:
+        s.close()
+    events = sum(o["events"] for o in obs)
+    return {"events": events, "seconds": el, "obs": obs, "roofline": rl,
+            "windows": sum(o["window"] for o in obs)}
 
 
 def cpu_baseline(wl, seconds):
@@ -63,8 +114,7 @@ def cpu_baseline(wl, seconds):
     from the workload's own initial state, until `seconds` of CPU time."""
     import numpy as np
     import oracle
-    kind = wl["kind"]
-    if kind == "flip":
+    if wl["kind"] == "flip":
         k_a, k_d, J, h, beta = wl["params"]
         model = oracle.Model("flip", wl["Lx"], wl["Ly"], k_a=k_a, k_d=k_d, J=J, h=h, beta=beta)
     else:
@@ -73,24 +123,105 @@ def cpu_baseline(wl, seconds):
     b = wl["b"]
     cmap = oracle.colour_map(model, b, b, wl["n_colours"])
     cols, durs, _ = oracle.schedule(wl["split"], wl["n_colours"], wl["dt"], wl["T"])
-    if wl["init"] == "bernoulli":
-        lat = oracle.init_bernoulli(model.N, 0.5, 0, 0)
-    else:
-        lat = np.zeros(model.N, np.uint8)
+    lat = oracle.init_bernoulli(model.N, 0.5, 0, 0) if wl["init"] == "bernoulli" else np.zeros(model.N, np.uint8)
     t0 = time.process_time()
-    w = 0
-    events = 0
-    chunk = 2
+    w = events = 0
     while w < len(cols) and time.process_time() - t0 < seconds:
-        n = min(chunk, len(cols) - w)
+        n = min(2, len(cols) - w)
         res = oracle.fs_run(model, lat, b, b, cmap, wl["n_colours"], cols[w:w + n], durs[w:w + n], 0, 0, w0=w)
         lat = res["lattice"]
         events += res["events"]
         w += n
     el = time.process_time() - t0
     return {"value": events / el, "unit": "events/s", "cores": 1, "kind": "oracle",
-            "sample": f"{wl['name']}: windows [0,{w}) of {len(cols)} of replica 0, single-threaded, "
-                      f"{events} events in {el:.1f} s CPU"}
+            "sample": f"{wl['name']}: windows [0,{w}) of {len(cols)} of replica 0 from the same start, "
+                      f"single-threaded, {events} events in {el:.1f} s CPU"}
+
+
+def bench_batched(F, ctx, n_jobs, stride, chunk=50):
+    """512 (n_jobs) Ising replicas in one packed launch per window vs the same
+    replicas advanced one at a time; every job's final lattice compared."""
+    import hashlib
+    from paper_1105_4673_amd import autotune, workloads
+    jobs = workloads.c3_jobs(n=n_jobs)
+
+    def make_all(sel):
+        out = []
+        for j in sel:
+            s = make_sim(F, ctx, j)
+            init_sim(s, j)
+            out.append(s)
+        return out
+
+    best, timings = autotune.tune_waves_per_group(ctx, lambda: make_all(jobs[:96]))
+    log(f"autotune waves/group: {best} {timings}")
+    sims = make_all(jobs)
+    handles = [s.handle for s in sims]
+    F.fskmc_sync(ctx)
+    F.fskmc_ctx_read_kernel_timing(ctx)
+    F.fskmc_ctx_set_kernel_timing(ctx, stride)
+    launches = 0
+    t0 = time.perf_counter()
+    while True:
+        left = max(s.windows()[0] - s.windows()[1] for s in sims)
+        if left == 0:
+            break
+        F.fskmc_batch_advance(ctx, handles, min(chunk, left))
+        launches += min(chunk, left)
+    F.fskmc_sync(ctx)
+    el = time.perf_counter() - t0
+    obs = [s.observe() for s in sims]
+    rl = roofline(F, ctx, "flip", 16, obs, launches, "k_sweep_batched<P=4,flip>")
+    F.fskmc_ctx_set_kernel_timing(ctx, 0)
+    ev_b = sum(o["events"] for o in obs)
+    dig_b = [hashlib.sha256(s.lattice().tobytes()).hexdigest() for s in sims]
+    for s in sims:
+        s.close()
+    log(f"batched: {ev_b} events in {el:.3f} s")
+
+    seq = make_all(jobs)
+    F.fskmc_sync(ctx)
+    t0 = time.perf_counter()
+    for s in seq:
+        s.run_to_end()
+    F.fskmc_sync(ctx)
+    el_s = time.perf_counter() - t0
+    obs_s = [s.observe() for s in seq]
+    ev_s = sum(o["events"] for o in obs_s)
+    dig_s = [hashlib.sha256(s.lattice().tobytes()).hexdigest() for s in seq]
+    for s in seq:
+        s.close()
+    log(f"sequential: {ev_s} events in {el_s:.3f} s")
+    identical = dig_b == dig_s and ev_b == ev_s
+    sites = sum(j["Lx"] * j["Ly"] for j in jobs)
+    return {"workload": f"ising_x{n_jobs}_edges128-1024_b16_lie_dt0.1_T10", "jobs": n_jobs, "sites": sites,
+            "value": ev_b / el, "unit": "events/s", "seconds": el, "events": ev_b,
+            "sequential_value": ev_s / el_s, "sequential_seconds": el_s,
+            "speedup_vs_sequential": (ev_b / el) / (ev_s / el_s), "bit_identical_to_sequential": identical,
+            "waves_per_group": best, "autotune_s_per_window": timings, "roofline": rl}
+
+
+def bench_served(F, ctx, rates, n_jobs, windows_per_step, budget_gib):
+    """Poisson request streams of mixed Ising / reaction jobs served with
+    continuous batching; time-to-result percentiles and aggregate events/s."""
+    from paper_1105_4673_amd import workloads
+    from paper_1105_4673_amd.serve import GpuBackend, Request, Server, summarize
+    out = []
+    for rate in rates:
+        reqs = [Request(i, spec, spec["arrival"]) for i, spec in enumerate(workloads.c4_requests(rate, n=n_jobs))]
+        srv = Server(GpuBackend(ctx), hbm_budget=int(budget_gib * (1 << 30)), max_slots=n_jobs,
+                     windows_per_step=windows_per_step)
+        t0 = time.perf_counter()
+        done = srv.run(reqs)
+        wall = time.perf_counter() - t0
+        s = summarize(done, wall)
+        s.update({"rate_jobs_per_s": rate, "requests": n_jobs, "batched_steps": srv.steps,
+                  "last_arrival_s": max(r.arrival for r in reqs),
+                  "sites_mean": sum(r.spec["Lx"] * r.spec["Ly"] for r in reqs) / n_jobs})
+        log(f"served rate {rate}/s: {s['jobs']} jobs, {s['events']} events in {wall:.2f} s, "
+            f"p50 {s['p50_time_to_result_s']:.3f} s p99 {s['p99_time_to_result_s']:.3f} s")
+        out.append(s)
+    return out
 
 
 def main():
@@ -102,10 +233,15 @@ def main():
     ap.add_argument("--dt", type=float, default=0.1)
     ap.add_argument("--split", type=int, default=0)
     ap.add_argument("--timing-stride", type=int, default=8,
-                    help="bracket every k-th sweep launch with HIP timing events")
+                    help="bracket every k-th sweep launch with kernel-side HIP timing events")
     ap.add_argument("--waves-per-group", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-jobs", type=int, default=512, help="0 skips the batched measurement")
+    ap.add_argument("--sweep", action="store_true", help="also time the other (J, dt, split) points")
+    ap.add_argument("--served-jobs", type=int, default=64, help="requests per arrival rate; 0 skips serving")
+    ap.add_argument("--served-rates", default="50,200,1000")
+    ap.add_argument("--served-windows-per-step", type=int, default=4)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -128,66 +264,53 @@ def main():
     from paper_1105_4673_amd import fskmc as F
     from paper_1105_4673_amd import workloads
 
-    wl = workloads.c1(J=args.J, dt=args.dt, split=args.split)
     torch.cuda.init()
-    stream = torch.cuda.current_stream()
-    ctx = F.fskmc_ctx_create(0, stream.cuda_stream)
+    ctx = F.fskmc_ctx_create(0, torch.cuda.current_stream().cuda_stream)
     F.fskmc_ctx_set_waves_per_group(ctx, args.waves_per_group)
-    sims = [make_sim(F, ctx, wl, replica=i) for i in range(args.warmup + args.steps)]
-    log(f"workload {wl['name']}: {sims[0].windows()[0]} windows per step")
-
-    for i in range(args.warmup):
-        run_once(F, sims[i], wl)
-        log(f"warmup step {i} done")
-    F.fskmc_sync(ctx)
-    F.fskmc_ctx_read_kernel_timing(ctx)  # discard
-    F.fskmc_ctx_set_kernel_timing(ctx, args.timing_stride)
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    obs = []
-    for i in range(args.steps):
-        obs.append(run_once(F, sims[args.warmup + i], wl))
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ms_total, n_timed = F.fskmc_ctx_read_kernel_timing(ctx)
-    F.fskmc_ctx_set_kernel_timing(ctx, 0)
-
-    events = sum(o["events"] for o in obs)
-    bw = sum(o["block_windows"] for o in obs)
-    wr = sum(o["writes"] for o in obs)
-    launches = sum(o["window"] for o in obs)
-    log(f"timed {args.steps} steps: {el:.3f} s, {events} events, {launches} sweep launches, "
-        f"{n_timed} timed launches avg {ms_total / max(n_timed, 1) * 1e3:.2f} us")
-    bytes_per_launch = hbm_bytes(wl["kind"], wl["b"], bw, wr) / launches
-    avg_launch_s = ms_total / 1e3 / max(n_timed, 1)
-    achieved = bytes_per_launch / avg_launch_s / 1e9
+    wl = workloads.c1(J=args.J, dt=args.dt, split=args.split)
+    log(f"workload {wl['name']}")
+    p = bench_plain(F, ctx, wl, args.steps, args.warmup, args.timing_stride)
+    log(f"plain: {args.steps} steps, {p['events']} events in {p['seconds']:.3f} s, "
+        f"kernel avg {p['roofline']['avg_launch_us']:.2f} us")
     result = {
         "metric": METRIC,
-        "value": events / el,
+        "value": p["events"] / p["seconds"],
         "unit": "events/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": el * 1e3 / args.steps,
+        "ms_per_step": p["seconds"] * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl["name"], "lattice": [wl["Lx"], wl["Ly"]], "block": [wl["b"], wl["b"]],
-                   "colours": wl["n_colours"], "windows_per_step": int(launches // args.steps),
-                   "events_per_step": events / args.steps, "waves_per_group": args.waves_per_group},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_sweep_single<4,16,16,flip>", "bytes_per_launch": bytes_per_launch,
-                     "avg_launch_us": avg_launch_s * 1e6, "timed_launches": n_timed},
+                   "colours": wl["n_colours"], "windows_per_step": p["windows"] // args.steps,
+                   "events_per_step": p["events"] / args.steps, "waves_per_group": args.waves_per_group},
+        "roofline": p["roofline"],
     }
+    if args.sweep:
+        sweep = []
+        for J in (0.5, 1.0, 2.0):
+            for dt in (0.01, 0.1, 1.0):
+                for split in (0, 1):
+                    w2 = workloads.c1(J=J, dt=dt, split=split)
+                    q = bench_plain(F, ctx, w2, 1, 1, 0)
+                    sweep.append({"workload": w2["name"], "value": q["events"] / q["seconds"],
+                                  "ms_per_step": q["seconds"] * 1e3, "events_per_step": q["events"]})
+                    log(f"sweep {w2['name']}: {q['events'] / q['seconds']:.3g} events/s")
+        result["sweep"] = sweep
+    if args.batched_jobs:
+        F.fskmc_ctx_set_waves_per_group(ctx, args.waves_per_group)
+        result["batched"] = bench_batched(F, ctx, args.batched_jobs, args.timing_stride)
+    if args.served_jobs:
+        F.fskmc_ctx_set_waves_per_group(ctx, args.waves_per_group)
+        result["served"] = bench_served(F, ctx, [float(r) for r in args.served_rates.split(",")], args.served_jobs,
+                                        args.served_windows_per_step, budget_gib=64.0)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
-    for s in sims:
-        s.close()
     F.fskmc_ctx_destroy(ctx)
     print(json.dumps(result), flush=True)
 

@@ -198,6 +198,15 @@ int fskmc_sync(fskmc_ctx* ctx);
  * kernels (1, 2, 4 or 8). */
 int fskmc_ctx_set_waves_per_group(fskmc_ctx* ctx, int waves);
 
+/* Knob that never changes results: with windows > 0, fskmc_sim_advance runs
+ * up to `windows` windows of one simulation inside a single persistent
+ * (cooperative) kernel in which each block waits only for the blocks it can
+ * interact with (the local synchronisation of Sec. 2.2) instead of a kernel
+ * boundary per window; 0 restores one launch per window.  A neighbour wait
+ * longer than two seconds aborts the kernel and the next synchronising call
+ * returns FSKMC_EDEVICE. */
+int fskmc_ctx_set_persistent(fskmc_ctx* ctx, int windows);
+
 /* Measurement aid.  With stride > 0, every stride-th sweep launch on this
  * context is bracketed by two HIP timing events recorded on the context
  * stream (stride 0 turns it off).  read returns the summed duration of the

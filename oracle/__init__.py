@@ -22,6 +22,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fskmc_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# a planted-mistake variant built by tests/test_oracle_plants.py (test hook)
+_LIB_OVERRIDE = os.environ.get("FSKMC_ORACLE_LIB")
 
 MODEL_FLIP = 1
 MODEL_ZGB = 2
@@ -31,8 +33,11 @@ GCC_FLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-f
              "-fexcess-precision=standard", "-Wall"]
 
 
-def build(force=True):
+def build(force=True, out=None, defines=()):
     """Compile the oracle's C part with gcc (test infrastructure)."""
+    if out is not None:
+        subprocess.check_call(["gcc"] + GCC_FLAGS + ["-D" + d for d in defines] + ["-o", out, _SRC, "-lm"])
+        return out
     if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
         return _LIB
     tmp = _LIB + ".tmp%d" % os.getpid()
@@ -52,9 +57,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        L = ctypes.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            L = ctypes.CDLL(_LIB_OVERRIDE)
+        else:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+            L = ctypes.CDLL(_LIB)
         P = ctypes.POINTER
         u32p, dblp, u8p, i64p, u64p, intp = (P(ctypes.c_uint32), P(ctypes.c_double), P(ctypes.c_uint8),
                                              P(ctypes.c_int64), P(ctypes.c_uint64), P(ctypes.c_int))

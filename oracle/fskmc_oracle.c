@@ -32,6 +32,13 @@
 #include <string.h>
 #include <math.h>
 
+/* Test hook: OR_PLANT selects one deliberate mistake; tests/test_oracle_plants.py
+ * builds such variants to show that the pins catch each of them.  It is 0 in
+ * every real build. */
+#ifndef OR_PLANT
+#define OR_PLANT 0
+#endif
+
 #define OR_OK 0
 #define OR_EINVAL (-1)
 #define OR_ENOMEM (-2)
@@ -63,7 +70,7 @@ void or_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
     int round;
     for (round = 0; round < 10; round++) {
         uint32_t hi0, lo0, hi1, lo1;
-        if (round > 0) {
+        if (round > 0 || OR_PLANT == 2) {
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
@@ -107,7 +114,7 @@ static void or_draw(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
  * after the z^10/21 term, then log u = e*ln2_hi + (e*ln2_lo + log m) with
  * ln 2 split so that e*ln2_hi is exact.                                      */
 static const double OR_LN2_HI = 0x1.62e42ff000000p-1;
-static const double OR_LN2_LO = -0x1.718432a1b0e26p-35;
+static const double OR_LN2_LO = (OR_PLANT == 8 ? 1.0 : -1.0) * 0x1.718432a1b0e26p-35;
 static const double OR_SQRT2 = 0x1.6a09e667f3bcdp+0;
 
 double or_log(double u)
@@ -161,7 +168,7 @@ static int or_neighbour(const or_model* M, int site, int d)
     case 0: x = (x + 1) % M->Lx; break;
     case 1: x = (x - 1 + M->Lx) % M->Lx; break;
     case 2: y = (y + 1) % M->Ly; break;
-    default: y = (y - 1 + M->Ly) % M->Ly; break;
+    default: y = OR_PLANT == 5 ? (y + 1) % M->Ly : (y - 1 + M->Ly) % M->Ly; break;
     }
     return y * M->Lx + x;
 }
@@ -176,6 +183,8 @@ static double or_flip_rate(const or_model* M, const uint8_t* lat, int site)
         n += lat[or_neighbour(M, site, d)];
     if (lat[site] == 0)
         return M->p[0];
+    if (OR_PLANT == 1)
+        return M->p[1] * exp(M->p[4] * (M->p[2] * (double)n + M->p[3]));
     return M->p[1] * exp(-(M->p[4] * (M->p[2] * (double)n + M->p[3])));
 }
 
@@ -200,7 +209,7 @@ static void or_zgb_channels(const or_model* M, const uint8_t* lat, int site, dou
         if (s == 0 && q == 0)
             ch[1 + d] = (1.0 - y) / 4.0;
         if ((s == 1 && q == 2) || (s == 2 && q == 1))
-            ch[5 + d] = kr / 4.0;
+            ch[5 + d] = OR_PLANT == 6 ? kr / 2.0 : kr / 4.0;
         if (s == 1 && q == 0)
             ch[9 + d] = D / 4.0;
     }
@@ -259,7 +268,7 @@ static int or_apply_event(const or_model* M, uint8_t* lat, int site, double tg, 
             changed[0] = site;
             return 1;
         }
-        d = (pick - 1) % 4;
+        d = OR_PLANT == 9 ? (pick - 1) / 4 : (pick - 1) % 4;
         y = or_neighbour(M, site, d);
         changed[0] = site;
         changed[1] = y;
@@ -356,7 +365,7 @@ static int or_tree_descend(const double* v, int nt, double* tg)
         if (t < L || Rr == 0.0) {
             k = 2 * k;
         } else {
-            t = t - L;
+            t = OR_PLANT == 3 ? t - Rr : t - L;
             k = 2 * k + 1;
         }
     }
@@ -583,7 +592,7 @@ int64_t or_schedule(int split, int n_colours, double dt, double T, uint32_t seed
                 dur = dt;
             } else if (split == OR_STRANG) {
                 col = c < n_colours ? c : 2 * (n_colours - 1) - c;
-                dur = (col == n_colours - 1) ? dt : h;
+                dur = (col == n_colours - 1 && OR_PLANT != 4) ? dt : h;
             } else {
                 double U, V;
                 or_draw((uint32_t)w, 0u, 0u, 3u, seed, replica, &U, &V);
@@ -668,7 +677,7 @@ int or_fs_run(const or_model* M, uint8_t* lat, int bx, int by, int n_colours, co
         int col = win_colour[i];
         for (m = 0; m < nb; m++) {
             uint32_t e = 0;
-            if (colour_map[m] == col) {
+            if (colour_map[m] == col || OR_PLANT == 7) {
                 e = or_block_window(M, lat, bx, by, m, NBX, win_dur[i], w0 + (uint64_t)i, seed, replica, v);
                 total += e;
             }

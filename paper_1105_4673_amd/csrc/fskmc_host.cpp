@@ -84,6 +84,10 @@ struct fskmc_ctx {
     size_t ev_used = 0;              // pairs recorded since the last harvest
     double timed_ms = 0.0;
     uint64_t timed_n = 0;
+    // persistent multi-window sweeps (0 = one launch per window)
+    int persist = 0;
+    int32_t* d_abort = nullptr;  // raised by the persistent kernel on a timed-out wait
+    int32_t* h_abort = nullptr;  // pinned copy, refreshed after each persistent launch
 };
 
 struct fskmc_sim {
@@ -113,6 +117,13 @@ struct fskmc_sim {
     int32_t* d_coff = nullptr;
     int8_t* d_wcol = nullptr;
     double* d_wdur = nullptr;
+    // persistent sweep: colour per block, next window per colour, interacting
+    // blocks, per-block epochs
+    std::vector<int32_t> next_part;  // [n_colours][n_windows+1]
+    int8_t* d_bcol = nullptr;
+    int32_t* d_next = nullptr;
+    int32_t* d_nbr = nullptr;
+    int32_t* d_epoch = nullptr;
 };
 
 namespace {
@@ -326,6 +337,10 @@ void free_sim_device(fskmc_sim* S)
     (void)hipFree(S->d_coff);
     (void)hipFree(S->d_wcol);
     (void)hipFree(S->d_wdur);
+    (void)hipFree(S->d_bcol);
+    (void)hipFree(S->d_next);
+    (void)hipFree(S->d_nbr);
+    (void)hipFree(S->d_epoch);
     S->d_lat = nullptr;
 }
 
@@ -407,11 +422,94 @@ int enqueue_window(fskmc_sim* S, uint64_t w)
     return FSKMC_OK;
 }
 
+// Windows [w0, w1) in one persistent kernel: epochs set to each block's first
+// window >= w0, the abort flag cleared, one cooperative launch, and the flag
+// copied back for the next synchronising call to check.
+int enqueue_persistent(fskmc_sim* S, uint64_t w0, uint64_t w1)
+{
+    fskmc_ctx* c = S->ctx;
+    hipStream_t st = c->stream;
+    HIP_TRY(launch_epoch_init(S->d_epoch, S->d_bcol, S->d_next, S->nb, (int)S->n_windows, (int)w0, st));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_abort), 1, 0u, st));
+    PersistArgs a;
+    a.lat = S->d_lat;
+    a.table = S->d_table;
+    a.cnt = S->d_cnt;
+    a.blocks = S->d_blocks;
+    a.colour_off = S->d_coff;
+    a.win_colour = S->d_wcol;
+    a.win_dur = S->d_wdur;
+    a.next_part = S->d_next;
+    a.nbr = S->d_nbr;
+    a.epoch = S->d_epoch;
+    a.abort_flag = c->d_abort;
+    a.Lx = S->lat.Lx;
+    a.Ly = S->lat.Ly;
+    a.NBX = S->NBX;
+    a.k0 = S->key.seed;
+    a.k1 = S->key.replica;
+    a.n_windows = (int)S->n_windows;
+    a.w0 = (int)w0;
+    a.w1 = (int)w1;
+    a.n_waves = 0;
+    a.wait_ticks = 200000000ull; // two seconds of the 100 MHz wall clock
+    const LaunchTiming tk = timing_begin(c);
+    HIP_TRY(launch_sweep_persistent(S->model, S->P, S->shape, c->wpg, a, S->max_per_colour, st, tk));
+    timing_end(c, tk);
+    HIP_TRY(hipMemcpyAsync(c->h_abort, c->d_abort, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    for (uint64_t w = w0; w < w1; ++w) {
+        const int col = S->win_colour[w];
+        S->block_windows += (uint64_t)(S->colour_off[col + 1] - S->colour_off[col]);
+    }
+    return FSKMC_OK;
+}
+
+// After a stream synchronisation: did a persistent sweep abort?
+int check_abort(fskmc_ctx* c)
+{
+    if (c->h_abort && *c->h_abort) {
+        *c->h_abort = 0;
+        return fail(FSKMC_EDEVICE, "persistent sweep aborted: a neighbour wait timed out");
+    }
+    return FSKMC_OK;
+}
+
+// Blocks that can interact with block m (their read/write sets meet): the
+// four edge neighbours for spin flip (the two in 1D), the eight surrounding
+// blocks for pair events.  Self and repeats (small periodic grids) dropped.
+void build_neighbours(const fskmc_sim& S, std::vector<int32_t>& nbr)
+{
+    nbr.assign((size_t)S.nb * 8, -1);
+    const bool pair = S.model == FSKMC_MODEL_ZGB;
+    for (int m = 0; m < S.nb; ++m) {
+        const int bi = m % S.NBX, bj = m / S.NBX;
+        int k = 0;
+        for (int dj = -1; dj <= 1; ++dj)
+            for (int di = -1; di <= 1; ++di) {
+                if (di == 0 && dj == 0)
+                    continue;
+                if (!pair && di != 0 && dj != 0)
+                    continue;
+                if (S.NBY == 1 && dj != 0)
+                    continue;
+                const int ni = (bi + di + S.NBX) % S.NBX, nj = (bj + dj + S.NBY) % S.NBY;
+                const int n = nj * S.NBX + ni;
+                if (n == m)
+                    continue;
+                bool seen = false;
+                for (int q = 0; q < k; ++q)
+                    seen = seen || nbr[(size_t)m * 8 + q] == n;
+                if (!seen)
+                    nbr[(size_t)m * 8 + k++] = n;
+            }
+    }
+}
+
 size_t footprint_of(int64_t N, int model, int nb, uint64_t n_windows, int n_colours)
 {
     const size_t tab = model == FSKMC_MODEL_FLIP ? 10 * 8 : 243 * 14 * 8;
-    return (size_t)N + tab + (size_t)nb * (sizeof(BlockCount) + 4) + (size_t)(n_colours + 1) * 4 +
-           (size_t)n_windows * (1 + 8);
+    return (size_t)N + tab + (size_t)nb * (sizeof(BlockCount) + 4 + 1 + 32 + 4) + (size_t)(n_colours + 1) * 4 +
+           (size_t)n_windows * (1 + 8) + (size_t)n_colours * (n_windows + 1) * 4;
 }
 
 }  // namespace
@@ -444,10 +542,13 @@ int fskmc_ctx_create(int device, void* hip_stream, fskmc_ctx** out)
     }
     if (hipMalloc((void**)&c->d_obs, 16 * sizeof(unsigned long long)) != hipSuccess ||
         hipHostMalloc((void**)&c->h_obs, 16 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
-        hipEventCreateWithFlags(&c->stage_free, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->stage_free, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc((void**)&c->d_abort, sizeof(int32_t)) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_abort, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
         fskmc_ctx_destroy(c);
         return fail(FSKMC_ENOMEM, "context allocation failed");
     }
+    *c->h_abort = 0;
     *out = c;
     return FSKMC_OK;
 }
@@ -461,6 +562,8 @@ int fskmc_ctx_destroy(fskmc_ctx* c)
         (void)hipStreamSynchronize(c->stream);
     (void)hipFree(c->d_obs);
     (void)hipHostFree(c->h_obs);
+    (void)hipFree(c->d_abort);
+    (void)hipHostFree(c->h_abort);
     (void)hipFree(c->d_jobs);
     (void)hipFree(c->d_items);
     (void)hipHostFree(c->h_stage);
@@ -471,6 +574,16 @@ int fskmc_ctx_destroy(fskmc_ctx* c)
     if (c->own_stream && c->stream)
         (void)hipStreamDestroy(c->stream);
     delete c;
+    return FSKMC_OK;
+}
+
+int fskmc_ctx_set_persistent(fskmc_ctx* c, int windows)
+{
+    if (!c)
+        return fail(FSKMC_EINVAL, "ctx is NULL");
+    if (windows < 0)
+        return fail(FSKMC_EINVAL, "windows must be >= 0");
+    c->persist = windows;
     return FSKMC_OK;
 }
 
@@ -514,7 +627,7 @@ int fskmc_sync(fskmc_ctx* c)
     if (!c)
         return fail(FSKMC_EINVAL, "ctx is NULL");
     HIP_TRY(hipStreamSynchronize(c->stream));
-    return FSKMC_OK;
+    return check_abort(c);
 }
 
 int fskmc_sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const void* params,
@@ -616,18 +729,36 @@ int fskmc_sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, co
             return fail(FSKMC_EINVAL, "rate %g is not finite or too large", r);
         }
     }
+    // persistent-sweep tables: next window of each colour, colour per block,
+    // interacting blocks
+    const size_t nw1 = (size_t)S->n_windows + 1;
+    S->next_part.assign((size_t)S->n_colours * nw1, (int32_t)S->n_windows);
+    for (int c = 0; c < S->n_colours; ++c)
+        for (int64_t w = (int64_t)S->n_windows - 1; w >= 0; --w)
+            S->next_part[c * nw1 + w] = S->win_colour[w] == c ? (int32_t)w : S->next_part[c * nw1 + w + 1];
+    std::vector<int8_t> bcol(S->cmap.begin(), S->cmap.end());
+    std::vector<int32_t> nbr;
+    build_neighbours(*S, nbr);
     (void)hipSetDevice(ctx->device);
     const int64_t N = n_sites(S->lat);
     if ((rc = dev_alloc(&S->d_lat, (size_t)N)) || (rc = dev_alloc(&S->d_table, S->table.size())) ||
         (rc = dev_alloc(&S->d_cnt, S->nb)) || (rc = dev_alloc(&S->d_blocks, S->blocks.size())) ||
         (rc = dev_alloc(&S->d_coff, S->colour_off.size())) || (rc = dev_alloc(&S->d_wcol, S->n_windows)) ||
-        (rc = dev_alloc(&S->d_wdur, S->n_windows))) {
+        (rc = dev_alloc(&S->d_wdur, S->n_windows)) || (rc = dev_alloc(&S->d_bcol, S->nb)) ||
+        (rc = dev_alloc(&S->d_next, S->next_part.size())) || (rc = dev_alloc(&S->d_nbr, nbr.size())) ||
+        (rc = dev_alloc(&S->d_epoch, S->nb))) {
         free_sim_device(S);
         delete S;
         return rc;
     }
     hipStream_t st = ctx->stream;
     hipError_t e = hipSuccess;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(S->d_bcol, bcol.data(), bcol.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(S->d_next, S->next_part.data(), S->next_part.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(S->d_nbr, nbr.data(), nbr.size() * 4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(S->d_table, S->table.data(), S->table.size() * 8, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
@@ -718,7 +849,7 @@ int fskmc_sim_get_lattice(fskmc_sim* S, uint8_t* host, size_t n)
         return fail(FSKMC_EINVAL, "lattice has %lld sites, got %zu bytes", (long long)n_sites(S->lat), n);
     HIP_TRY(hipMemcpyAsync(host, S->d_lat, n, hipMemcpyDeviceToHost, S->ctx->stream));
     HIP_TRY(hipStreamSynchronize(S->ctx->stream));
-    return FSKMC_OK;
+    return check_abort(S->ctx);
 }
 
 int fskmc_sim_advance(fskmc_sim* S, uint64_t n_windows)
@@ -727,6 +858,18 @@ int fskmc_sim_advance(fskmc_sim* S, uint64_t n_windows)
         return fail(FSKMC_EINVAL, "sim is NULL");
     if (n_windows > S->n_windows - S->window)
         return fail(FSKMC_ESTATE, "only %llu windows left before T", (unsigned long long)(S->n_windows - S->window));
+    if (S->ctx->persist > 0) {
+        uint64_t left = n_windows;
+        while (left > 0) {
+            const uint64_t k = std::min<uint64_t>(left, (uint64_t)S->ctx->persist);
+            int rc = enqueue_persistent(S, S->window, S->window + k);
+            if (rc)
+                return rc;
+            S->window += k;
+            left -= k;
+        }
+        return FSKMC_OK;
+    }
     for (uint64_t i = 0; i < n_windows; ++i) {
         int rc = enqueue_window(S, S->window);
         if (rc)
@@ -764,6 +907,8 @@ int fskmc_sim_observe(fskmc_sim* S, fskmc_obs* out)
                            c->stream));
     HIP_TRY(hipMemcpyAsync(c->h_obs, c->d_obs, 9 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    if (int rc = check_abort(c))
+        return rc;
     std::memset(out, 0, sizeof *out);
     out->n_sites = n_sites(S->lat);
     for (int k = 0; k < 3; ++k) {

@@ -51,6 +51,27 @@ struct JobDesc {
     uint32_t pad;
 };
 
+// Kernel arguments of the persistent multi-window sweep of one simulation.
+struct PersistArgs {
+    uint8_t* lat;
+    const double* table;
+    BlockCount* cnt;
+    const int32_t* blocks;      // block ids grouped by colour
+    const int32_t* colour_off;  // n_colours+1 offsets into blocks
+    const int8_t* win_colour;   // per window
+    const double* win_dur;      // per window
+    const int32_t* next_part;   // [n_colours][n_windows+1]: first window >= w of colour c
+    const int32_t* nbr;         // [n_blocks][8]: blocks that can interact, -1 padded
+    int32_t* epoch;             // [n_blocks]: next window each block takes part in
+    int32_t* abort_flag;        // raised by a wave whose wait timed out
+    int Lx, Ly, NBX;
+    uint32_t k0, k1;
+    int n_windows;
+    int w0, w1;
+    int n_waves;                // set by the launcher
+    unsigned long long wait_ticks;
+};
+
 // Optional kernel-side timing: when both events are set, the launch records
 // them at the kernel's own start and end (hipExtLaunchKernelGGL).
 struct LaunchTiming {
@@ -63,6 +84,10 @@ hipError_t launch_sweep_single(int model, int P, int shape, int wpg, const Sweep
 hipError_t launch_sweep_batched(int model, int P, int shape, int wpg, const JobDesc* jobs,
                                 const uint32_t* item_job, uint32_t n_items, uint64_t step,
                                 hipStream_t s, LaunchTiming tm);
+hipError_t launch_sweep_persistent(int model, int P, int shape, int wpg, const PersistArgs& a,
+                                   int max_blocks_per_colour, hipStream_t s, LaunchTiming tm);
+hipError_t launch_epoch_init(int32_t* epoch, const int8_t* bcol, const int32_t* next_part, int nb, int n_windows,
+                             int w0, hipStream_t s);
 hipError_t launch_init(uint8_t* lat, int64_t n, int kind, double p, uint32_t k0, uint32_t k1,
                        hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);

@@ -680,6 +680,65 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_batched(const JobDesc* __res
                                    jd.k1, (uint32_t)w, jd.win_dur[w], lds + wid * C::LDS);
 }
 
+// Persistent multi-window sweep of one simulation (cooperative launch: every
+// wave is resident).  Windows [w0, w1) run in order inside the kernel and the
+// colour barrier becomes a neighbour-only wait, the local synchronisation of
+// Sec. 2.2 stage 2: before block m runs window w, each block that can
+// interact with it must have finished all its windows before w.  epoch[n] is
+// the next window block n takes part in, published with agent-scope release
+// after its block-window and read with agent-scope acquire.  Same-colour
+// blocks of one window never interact, windows only depend on earlier ones,
+// so every wait ends; a wait longer than wait_ticks (100 MHz wall clock)
+// raises the abort flag and every wave leaves.
+template <int P, int BX, int BY, int MODEL, int WPG>
+__global__ __launch_bounds__(64 * WPG) void k_sweep_persistent(PersistArgs a)
+{
+    using C = Cfg<P, BX, BY, MODEL>;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[WPG * C::LDS];
+    const int wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int gw = (int)xcd_order(blockIdx.x, gridDim.x) * WPG + wid;
+    for (int w = a.w0; w < a.w1; ++w) {
+        const int c = a.win_colour[w];
+        const int beg = a.colour_off[c], count = a.colour_off[c + 1] - beg;
+        const int nxt = a.next_part[c * (a.n_windows + 1) + w + 1];
+        for (int k = gw; k < count; k += a.n_waves) {
+            const int m = a.blocks[beg + k];
+            if (lane < 8) {
+                const int nb = a.nbr[m * 8 + lane];
+                if (nb >= 0) {
+                    const uint64_t t0 = wall_clock64();
+                    while (__hip_atomic_load(&a.epoch[nb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < w) {
+                        if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                            break;
+                        if (wall_clock64() - t0 > a.wait_ticks) {
+                            __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+            }
+            if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                return;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            block_window<P, BX, BY, MODEL>(a.lat, a.table, a.cnt, a.Lx, a.Ly, m, a.NBX, a.k0, a.k1, (uint32_t)w,
+                                           a.win_dur[w], lds + wid * C::LDS);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (lane == 0)
+                __hip_atomic_store(&a.epoch[m], nxt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// epoch[m] = the first window >= w0 that block m takes part in.
+__global__ void k_epoch_init(int32_t* epoch, const int8_t* bcol, const int32_t* next_part, int nb, int n_windows,
+                             int w0)
+{
+    for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < nb; m += gridDim.x * blockDim.x)
+        epoch[m] = next_part[bcol[m] * (n_windows + 1) + w0];
+}
+
 // ---------------------------------------------------------------------------
 // Initial states and fills.
 __global__ void k_init(uint8_t* lat, int64_t n, int kind, double p, uint32_t k0, uint32_t k1)
@@ -860,6 +919,83 @@ hipError_t launch_sweep_batched(int model, int P, int shape, int wpg, const JobD
 #undef FSKMC_SW
 }
 
+// Cooperative launch of the persistent sweep: as many workgroups as can be
+// resident at once (occupancy x CUs), but no more than the largest colour
+// class needs.
+template <int P, int BX, int BY, int MODEL, int WPG>
+static hipError_t persist_launch(PersistArgs a, int max_blocks_per_colour, hipStream_t s, LaunchTiming tm)
+{
+    auto kern = k_sweep_persistent<P, BX, BY, MODEL, WPG>;
+    static int resident_groups = 0;
+    if (resident_groups == 0) {
+        int per_cu = 0, dev = 0, cus = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * WPG, 0);
+        if (e != hipSuccess)
+            return e;
+        if ((e = hipGetDevice(&dev)) != hipSuccess ||
+            (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+            return e;
+        resident_groups = per_cu * cus;
+        if (resident_groups <= 0)
+            return hipErrorInvalidConfiguration;
+    }
+    const int want = (max_blocks_per_colour + WPG - 1) / WPG;
+    const int groups = want < resident_groups ? want : resident_groups;
+    a.n_waves = groups * WPG;
+    void* args[] = {&a};
+    if (tm.start)
+        (void)hipEventRecord(tm.start, s);
+    hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(groups), dim3(64 * WPG),
+                                              args, 0, s);
+    if (tm.stop)
+        (void)hipEventRecord(tm.stop, s);
+    return e;
+}
+
+template <int MODEL, int WPG>
+static hipError_t persist_dispatch(int P, int shape, const PersistArgs& a, int maxpc, hipStream_t s, LaunchTiming tm)
+{
+    if (shape == SHAPE_SQ) {
+        if (P == 1)
+            return persist_launch<1, 8, 8, MODEL, WPG>(a, maxpc, s, tm);
+        if (P == 4)
+            return persist_launch<4, 16, 16, MODEL, WPG>(a, maxpc, s, tm);
+        if (P == 16)
+            return persist_launch<16, 32, 32, MODEL, WPG>(a, maxpc, s, tm);
+        return hipErrorInvalidValue;
+    }
+    if constexpr (MODEL != MODEL_FLIP) {
+        return hipErrorInvalidValue;
+    } else {
+        if (P == 1)
+            return persist_launch<1, 64, 1, MODEL, WPG>(a, maxpc, s, tm);
+        if (P == 4)
+            return persist_launch<4, 256, 1, MODEL, WPG>(a, maxpc, s, tm);
+        if (P == 16)
+            return persist_launch<16, 1024, 1, MODEL, WPG>(a, maxpc, s, tm);
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sweep_persistent(int model, int P, int shape, int wpg, const PersistArgs& a,
+                                   int max_blocks_per_colour, hipStream_t s, LaunchTiming tm)
+{
+#define FSKMC_SW(MOD)                                                                    \
+    switch (wpg) {                                                                       \
+    case 1: return persist_dispatch<MOD, 1>(P, shape, a, max_blocks_per_colour, s, tm); \
+    case 2: return persist_dispatch<MOD, 2>(P, shape, a, max_blocks_per_colour, s, tm); \
+    case 4: return persist_dispatch<MOD, 4>(P, shape, a, max_blocks_per_colour, s, tm); \
+    case 8: return persist_dispatch<MOD, 8>(P, shape, a, max_blocks_per_colour, s, tm); \
+    default: return hipErrorInvalidValue;                                                \
+    }
+    if (model == MODEL_FLIP) {
+        FSKMC_SW(MODEL_FLIP)
+    } else {
+        FSKMC_SW(MODEL_ZGB)
+    }
+#undef FSKMC_SW
+}
+
 static unsigned grid_for(int64_t n, int bs)
 {
     int64_t g = (n + bs - 1) / bs;
@@ -889,6 +1025,14 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s)
     if (n <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_epoch_init(int32_t* epoch, const int8_t* bcol, const int32_t* next_part, int nb, int n_windows,
+                             int w0, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_epoch_init, dim3(grid_for(nb, 256)), dim3(256), 0, s, epoch, bcol, next_part, nb, n_windows,
+                       w0);
     return hipGetLastError();
 }
 

@@ -329,3 +329,35 @@ def test_batch_equals_alone(F, orc, ctx):
         assert a.observe()["events"] == b.observe()["events"]
         a.close()
         b.close()
+
+
+@pytest.mark.parametrize("case", [
+    (FLIP, 64, 64, (1.0, 1.0, 1.0, 0.0, 1.0), 8, 2, 0.1, 10.0, "lie", "empty", 7),
+    (FLIP, 256, 256, (1.0, 1.0, 0.5, 0.2, 1.0), 16, 2, 0.1, 100.0, "strang", "bernoulli", 16),
+    (FLIP, 256, 256, (1.0, 1.0, 2.0, -0.3, 1.0), 32, 2, 1.0, 100.0, "random", "bernoulli", 5),
+    (FLIP, 4096, 1, (1.0, 1.0, 1.0, -0.5, 1.0), 256, 2, 1.0, 100.0, "lie", "bernoulli", 9),
+    (ZGB, 256, 256, (0.5, 1000.0, 10.0), 32, 4, 0.05, 10.0, "strang", "empty", 11),
+], ids=["flip64-b8", "flip256-b16-strang", "flip256-b32-random", "flip1d-b256", "zgb256-b32"])
+def test_persistent_sweep_bitwise(F, orc, ctx, case):
+    """Several windows inside one persistent kernel (neighbour-only waits
+    instead of a launch per window) give the oracle's bits."""
+    kind, Lx, Ly, prm, b, ncol, dt, T, split, init, chunk = case
+    F.fskmc_ctx_set_persistent(ctx, chunk)
+    try:
+        p = Pair(F, orc, ctx, kind, Lx, Ly, prm, b, ncol, dt, T, split, init=init, seed=0, replica=3)
+        p.step_compare_end(3 * chunk + 2)
+        p.step_compare_end(chunk)
+        F.fskmc_sync(ctx)
+    finally:
+        F.fskmc_ctx_set_persistent(ctx, 0)
+
+
+def test_persistent_full_run_config1(F, orc, ctx):
+    """The 1024^2 workload's first 40 windows as one persistent launch."""
+    F.fskmc_ctx_set_persistent(ctx, 40)
+    try:
+        p = Pair(F, orc, ctx, FLIP, 1024, 1024, (1.0, 1.0, 1.0, 0.0, 1.0), 16, 2, 0.1, 100.0, "lie",
+                 init="bernoulli", seed=0, replica=0)
+        p.step_compare_end(40)
+    finally:
+        F.fskmc_ctx_set_persistent(ctx, 0)
