@@ -595,7 +595,7 @@ int64_t or_schedule(int split, int n_colours, double dt, double T, uint32_t seed
                 dur = (col == n_colours - 1 && OR_PLANT != 4) ? dt : h;
             } else {
                 double U, V;
-                or_draw((uint32_t)w, 0u, 0u, 3u, seed, replica, &U, &V);
+                or_draw((uint32_t)(OR_PLANT == 10 ? k : w), 0u, 0u, 3u, seed, replica, &U, &V);
                 col = (int)(V * (double)n_colours);
                 dur = dt;
             }

@@ -19,9 +19,14 @@ What the paper and the mathematics fix, independently of the oracle's code:
   error2), checked deterministically on the split propagator built from the
   oracle's own window list.
 * The decomposition checker enforces closure independence (Sec. 2.1 remark).
+* The random schedule (Sec. 3.1): its replica law is the averaged one-window
+  propagator; its mean local error is the (A1 - A2)^2 term of Sec. 4.1 while
+  Lie's is the commutator, so Lie wins at equal step and more so for larger
+  cells (eq. pcscompare).
 """
 import numpy as np
 import pytest
+import scipy.linalg
 
 import oracle as _o
 from oracle import exact
@@ -196,3 +201,117 @@ def test_fs_matches_serial_at_small_step_reaction(orc):
     for c in range(3):
         se = np.sqrt(fs_end[:, c].var(ddof=1) / R + ser[:, c].var(ddof=1) / R)
         assert abs(fs_end[:, c].mean() - ser[:, c].mean()) <= 3 * se
+
+
+def test_fs_random_schedule_matches_averaged_propagator(orc):
+    """Random schedule (Sec. 3.1, eq. SLPCS): every replica draws its own
+    colour sequence, uniform and independent per window, so the law over
+    replicas is p0 M^w with M = (1/K) sum_c exp(dt Q_c), the one-window form
+    of the averaged operator (eq. averaged).  The step is large enough that
+    this law differs from the serial one and from the Lie scheme's by more
+    than 6 standard errors."""
+    kind, Lx, Ly, bx, by, ncol = "flip", 2, 4, 1, 2, 2
+    cmap = np.array([0, 1, 1, 0], np.int32)
+    model = orc.Model(kind, Lx, Ly, k_a=1.0, k_d=1.0, J=1.5, h=-0.5, beta=1.0)
+    dt, T, R = 1.0, 2.0, 3000
+    lat0 = np.zeros(model.N, np.uint8)
+    sample, seqs = [], set()
+    for r in range(R):
+        cols, durs, ends = orc.schedule(_o.RANDOM, ncol, dt, T, 0, r)
+        seqs.add(tuple(cols))
+        sample.append(orc.fs_run(model, lat0, bx, by, cmap, ncol, cols, durs, 0, r, observe_flags=ends)["obs"])
+    sample = np.array(sample, dtype=np.float64)
+    assert len(seqs) == 2 ** 4        # 4 windows, every colour sequence occurs
+    Qc = _colour_generators(kind, model.params, Lx, Ly, bx, by, cmap, ncol)
+    M = sum(scipy.linalg.expm(dt * q) for q in Qc) / ncol
+    ov = exact.observable_vectors(kind, Lx, Ly)
+    p = delta_state(kind, lat0)
+    for k in range(int(T / dt)):
+        for _ in range(ncol):
+            p = p @ M
+        mean, var = moments(p, ov)
+        assert_within_3se(sample[:, k, :], mean, var, (1, 4), label=("random", k))
+    ms, vs = moments(p, ov)
+    me, _ = moments(exact.propagate(delta_state(kind, lat0), exact.generator(kind, model.params, Lx, Ly), T), ov)
+    cols, durs, _ = orc.schedule(_o.LIE, ncol, dt, T)
+    ml, _ = moments(exact.split_propagate(delta_state(kind, lat0), Qc, cols, durs), ov)
+    for other in (me, ml):
+        assert max(abs(ms[c] - other[c]) / np.sqrt(vs[c] / R) for c in (1, 4)) > 6.0
+
+
+def test_random_schedule_colours_uniform_and_independent(orc):
+    """Colour draws of the random schedule: uniform over K colours, the pair
+    of consecutive windows uniform over K^2 (independence), chi-square at the
+    0.1% level; the replica key changes the sequence."""
+    from scipy.stats import chisquare
+    for K in (2, 4):
+        cols = np.concatenate([orc.schedule(_o.RANDOM, K, 0.5, 100.0, 0, r)[0] for r in range(20)])
+        assert chisquare(np.bincount(cols, minlength=K)).pvalue > 1e-3
+        pairs = cols[:-1] * K + cols[1:]
+        assert chisquare(np.bincount(pairs, minlength=K * K)).pvalue > 1e-3
+    a = orc.schedule(_o.RANDOM, 2, 0.5, 100.0, 0, 0)[0]
+    b = orc.schedule(_o.RANDOM, 2, 0.5, 100.0, 0, 1)[0]
+    c = orc.schedule(_o.RANDOM, 2, 0.5, 100.0, 1, 0)[0]
+    assert not np.array_equal(a, b) and not np.array_equal(a, c)
+
+
+def test_random_schedule_mean_local_error():
+    """Sec. 4.1: averaged over the colours of two windows, the local error
+    against exp(dt (A1 + A2)) is (1/4)(A1 - A2)^2 dt^2 + O(dt^3); the Lie
+    product's is (1/2)[A1, A2] dt^2 + O(dt^3).  Checked on the coverage of a
+    2x4 lattice: the remainder divided by dt^2 shrinks linearly with dt."""
+    Lx, Ly, bx, by = 2, 4, 1, 2
+    prm = (1.0, 1.0, 1.5, -0.5, 1.0)
+    cmap = np.array([0, 1, 1, 0], np.int32)
+    A = [exact.generator("flip", prm, Lx, Ly, owner=exact.site_owner_by_colour(Lx, Ly, bx, by, cmap, c))
+         for c in range(2)]
+    f = exact.observable_vectors("flip", Lx, Ly)[:, 1] / (Lx * Ly)
+    lead_rnd = 0.25 * (A[0] - A[1]) @ ((A[0] - A[1]) @ f)
+    lead_lie = 0.5 * (A[0] @ (A[1] @ f) - A[1] @ (A[0] @ f))
+    assert np.abs(lead_rnd).max() > 0.1 and np.abs(lead_lie).max() > 0.1
+    rem = {"rnd": [], "lie": []}
+    for dt in (0.02, 0.01, 0.005):
+        E = [scipy.linalg.expm(dt * a) for a in A]
+        ref = scipy.linalg.expm(dt * (A[0] + A[1])) @ f
+        rnd = 0.25 * sum(E[i] @ (E[j] @ f) for i in range(2) for j in range(2)) - ref
+        lie = E[0] @ (E[1] @ f) - ref
+        rem["rnd"].append(np.abs(rnd / dt ** 2 - lead_rnd).max())
+        rem["lie"].append(np.abs(lie / dt ** 2 - lead_lie).max())
+    for k, r in rem.items():
+        ratios = np.array(r[:-1]) / np.array(r[1:])
+        assert np.all(np.abs(ratios - 2.0) < 0.2), (k, r)
+
+
+def test_pcs_compare_lie_allows_larger_step(orc):
+    """Sec. 4.1, eqs. lietimestep, randomtimestep, pcscompare: the Lie error
+    carries the commutator, which only the cell boundaries feed (eq.
+    lieboundary, O(1/q) for cells of q sites), while the random schedule's
+    mean error carries (A1 - A2)^2, which is O(1).  On a 12-site ring (J = 1,
+    empty start, T = 1, coverage): the random schedule is first order, Lie is
+    more accurate at the same step, and its advantage grows with q."""
+    import scipy.sparse.linalg as spl
+    N, prm, T = 12, (1.0, 1.0, 1.0, -0.5, 1.0), 1.0
+    f = exact.observable_vectors("flip", N, 1)[:, 1] / N
+    p0 = np.zeros(2 ** N)
+    p0[0] = 1.0
+    pe = spl.expm_multiply((exact.generator("flip", prm, N, 1, sparse=True).T * T).tocsr(), p0) @ f
+    adv = []
+    for q in (1, 2, 3, 6):
+        cmap = np.array([i % 2 for i in range(N // q)], np.int32)
+        At = [(exact.generator("flip", prm, N, 1, owner=exact.site_owner_by_colour(N, 1, q, 1, cmap, c),
+                               sparse=True).T).tocsr() for c in range(2)]
+        err_r, err_l = [], []
+        for dt in (0.1, 0.05):
+            cols, durs, _ = orc.schedule(_o.LIE, 2, dt, T)
+            p = p0
+            for c, d in zip(cols, durs):
+                p = spl.expm_multiply(At[c] * d, p)
+            err_l.append(abs(p @ f - pe))
+            p = p0
+            for _ in range(2 * int(round(T / dt))):
+                p = 0.5 * (spl.expm_multiply(At[0] * dt, p) + spl.expm_multiply(At[1] * dt, p))
+            err_r.append(abs(p @ f - pe))
+        assert abs(err_r[0] / err_r[1] - 2.0) < 0.2, (q, err_r)
+        assert err_l[0] < err_r[0] and err_l[1] < err_r[1], (q, err_l, err_r)
+        adv.append(err_r[0] / err_l[0])
+    assert all(b > a for a, b in zip(adv, adv[1:])), adv

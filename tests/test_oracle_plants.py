@@ -1,7 +1,8 @@
 """The oracle's pins have teeth: a variant of the oracle built with one
 plausible mistake (a wrong sign, a dropped guard, a wrong neighbour index, a
 wrong half step, a wrong factor, a missing colour test, a wrong constant, a
-wrong key schedule, a transposed direction) must fail at least one pin.
+wrong key schedule, a transposed direction, a colour
+drawn at the wrong rate) must fail at least one pin.
 
 Each variant is compiled on the CPU into a temporary library and the relevant
 pin tests are run against it in a child process."""
@@ -34,6 +35,9 @@ PLANTS = {
         ["test_oracle_rng.py::test_log_special_values", "test_oracle_rng.py::test_log_accuracy_on_uniforms"]),
     9: ("pair partner direction from the channel group instead of the direction",
         ["test_oracle_serial.py::test_serial_matches_master_equation"]),
+    10: ("random schedule drawing one colour per step instead of per window",
+         ["test_oracle_fs.py::test_random_schedule_colours_uniform_and_independent",
+          "test_oracle_fs.py::test_fs_random_schedule_matches_averaged_propagator"]),
 }
 
 
