@@ -87,7 +87,7 @@ def roofline(F, ctx, kind, b, obs_list, launches, kernel_name):
             "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg * 1e6, "timed_launches": n_timed}
 
 
-def bench_plain(F, ctx, wl, steps, warmup, stride):
+def bench_plain(F, ctx, wl, steps, warmup, stride, persist=0):
     sims = [make_sim(F, ctx, wl, replica=i) for i in range(warmup + steps)]
     for i in range(warmup):
         run_once(F, sims[i], wl)
@@ -99,8 +99,13 @@ def bench_plain(F, ctx, wl, steps, warmup, stride):
     obs = [run_once(F, sims[warmup + i], wl) for i in range(steps)]
     F.fskmc_sync(ctx)
     el = time.perf_counter() - t0
-    rl = roofline(F, ctx, wl["kind"], wl["b"], obs, sum(o["window"] for o in obs),
-                  f"k_sweep_single<P={wl['b'] ** 2 // 64},{wl['kind']}>")
+    if persist > 0:
+        launches = sum(-(-o["window"] // persist) for o in obs)
+        kname = f"k_sweep_persistent<P={wl['b'] ** 2 // 64},{wl['kind']}> ({persist} windows per launch)"
+    else:
+        launches = sum(o["window"] for o in obs)
+        kname = f"k_sweep_single<P={wl['b'] ** 2 // 64},{wl['kind']}>"
+    rl = roofline(F, ctx, wl["kind"], wl["b"], obs, launches, kname)
     F.fskmc_ctx_set_kernel_timing(ctx, 0)
     for s in sims:
         s.close()
@@ -235,6 +240,8 @@ def main():
     ap.add_argument("--timing-stride", type=int, default=8,
                     help="bracket every k-th sweep launch with kernel-side HIP timing events")
     ap.add_argument("--waves-per-group", type=int, default=2)
+    ap.add_argument("--persistent", type=int, default=0,
+                    help="windows per persistent launch for single-lattice runs (0: one launch per window)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-jobs", type=int, default=512, help="0 skips the batched measurement")
@@ -267,9 +274,10 @@ def main():
     torch.cuda.init()
     ctx = F.fskmc_ctx_create(0, torch.cuda.current_stream().cuda_stream)
     F.fskmc_ctx_set_waves_per_group(ctx, args.waves_per_group)
+    F.fskmc_ctx_set_persistent(ctx, args.persistent)
     wl = workloads.c1(J=args.J, dt=args.dt, split=args.split)
     log(f"workload {wl['name']}")
-    p = bench_plain(F, ctx, wl, args.steps, args.warmup, args.timing_stride)
+    p = bench_plain(F, ctx, wl, args.steps, args.warmup, args.timing_stride, args.persistent)
     log(f"plain: {args.steps} steps, {p['events']} events in {p['seconds']:.3f} s, "
         f"kernel avg {p['roofline']['avg_launch_us']:.2f} us")
     result = {
@@ -287,7 +295,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["name"], "lattice": [wl["Lx"], wl["Ly"]], "block": [wl["b"], wl["b"]],
                    "colours": wl["n_colours"], "windows_per_step": p["windows"] // args.steps,
-                   "events_per_step": p["events"] / args.steps, "waves_per_group": args.waves_per_group},
+                   "events_per_step": p["events"] / args.steps, "waves_per_group": args.waves_per_group,
+                   "persistent_windows_per_launch": args.persistent},
         "roofline": p["roofline"],
     }
     if args.sweep:
@@ -296,11 +305,12 @@ def main():
             for dt in (0.01, 0.1, 1.0):
                 for split in (0, 1):
                     w2 = workloads.c1(J=J, dt=dt, split=split)
-                    q = bench_plain(F, ctx, w2, 1, 1, 0)
+                    q = bench_plain(F, ctx, w2, 1, 1, 0, args.persistent)
                     sweep.append({"workload": w2["name"], "value": q["events"] / q["seconds"],
                                   "ms_per_step": q["seconds"] * 1e3, "events_per_step": q["events"]})
                     log(f"sweep {w2['name']}: {q['events'] / q['seconds']:.3g} events/s")
         result["sweep"] = sweep
+    F.fskmc_ctx_set_persistent(ctx, 0)  # batched and served runs use one packed launch per window
     if args.batched_jobs:
         F.fskmc_ctx_set_waves_per_group(ctx, args.waves_per_group)
         result["batched"] = bench_batched(F, ctx, args.batched_jobs, args.timing_stride)

@@ -185,6 +185,73 @@ __device__ __forceinline__ void store_seg(uint8_t* p, const Seg<P>& s)
     }
 }
 
+// Lattice accesses that are coherent across CUs and XCDs by themselves
+// (relaxed agent-scope atomics: each load and store goes to the coherence
+// point), used where other waves of the same kernel read what this wave
+// wrote; no whole-cache write-back or invalidation is needed around them.
+template <typename T>
+__device__ __forceinline__ T coh_load(const T* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void coh_store(T* p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int P, bool COH>
+__device__ __forceinline__ Seg<P> gload_seg(const uint8_t* p)
+{
+    if constexpr (!COH) {
+        return load_seg<P>(p);
+    } else {
+        Seg<P> s;
+        if constexpr (P == 1) {
+            s.w[0] = coh_load(p);
+        } else {
+#pragma unroll
+            for (int k = 0; k < P / 4; ++k)
+                s.w[k] = coh_load(reinterpret_cast<const uint32_t*>(p) + k);
+        }
+        return s;
+    }
+}
+
+template <int P, bool COH>
+__device__ __forceinline__ void gstore_seg(uint8_t* p, const Seg<P>& s)
+{
+    if constexpr (!COH) {
+        store_seg<P>(p, s);
+    } else {
+        if constexpr (P == 1) {
+            coh_store(p, (uint8_t)s.w[0]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < P / 4; ++k)
+                coh_store(reinterpret_cast<uint32_t*>(p) + k, s.w[k]);
+        }
+    }
+}
+
+template <bool COH>
+__device__ __forceinline__ uint32_t gload_byte(const uint8_t* p)
+{
+    if constexpr (COH)
+        return coh_load(p);
+    else
+        return *p;
+}
+
+template <bool COH>
+__device__ __forceinline__ void gstore_byte(uint8_t* p, uint32_t v)
+{
+    if constexpr (COH)
+        coh_store(p, (uint8_t)v);
+    else
+        *p = (uint8_t)v;
+}
+
 // Compile-time geometry of one sweep variant.  BX x BY = 64 P sites; lane j
 // owns leaves [jP, (j+1)P), i.e. row j / (BX/P), columns (j % (BX/P)) P + q.
 template <int P, int BX, int BY, int MODEL>
@@ -560,7 +627,8 @@ __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const
 // One block-window of the streaming sweep: stage block + halo from the
 // lattice into LDS, run the SSA window, write back what may have changed
 // (the block for spin flip; block and halo for pair events), update counters.
-template <int P, int BX, int BY, int MODEL>
+// COH: lattice accesses coherent across the device (persistent sweep).
+template <int P, int BX, int BY, int MODEL, bool COH = false>
 __device__ __forceinline__ void block_window(uint8_t* __restrict__ lat, const double* __restrict__ table, BlockCount* cnt, int Lx,
                              int Ly, int m, int NBX, uint32_t k0, uint32_t k1, uint32_t w, double dur, uint8_t* lds)
 {
@@ -587,17 +655,17 @@ __device__ __forceinline__ void block_window(uint8_t* __restrict__ lat, const do
     uint8_t* gtop = lat + (size_t)(gy == 0 ? Ly - 1 : gy - 1) * sLx + gx;
     uint8_t* gbot = lat + (size_t)(gy + 1 == Ly ? 0 : gy + 1) * sLx + gx;
     {
-        const Seg<P> own = load_seg<P>(grow + gx);
+        const Seg<P> own = gload_seg<P, COH>(grow + gx);
         Seg<P> top, bot;
         uint32_t lb = 0, rb = 0;
         if (has_top)
-            top = load_seg<P>(gtop);
+            top = gload_seg<P, COH>(gtop);
         if (has_bot)
-            bot = load_seg<P>(gbot);
+            bot = gload_seg<P, COH>(gbot);
         if (has_l)
-            lb = grow[xl];
+            lb = gload_byte<COH>(grow + xl);
         if (has_r)
-            rb = grow[xr];
+            rb = gload_byte<COH>(grow + xr);
         store_seg<P>(tile + tb, own);
         if (has_top)
             store_seg<P>(tile + tb - C::S, top);
@@ -613,16 +681,16 @@ __device__ __forceinline__ void block_window(uint8_t* __restrict__ lat, const do
     const uint32_t e = ssa_window<P, BX, BY, MODEL>(tile, tab, table, (uint32_t)m, w, dur, k0, k1);
 
     if (e > 0) {
-        store_seg<P>(grow + gx, load_seg<P>(tile + tb));
+        gstore_seg<P, COH>(grow + gx, load_seg<P>(tile + tb));
         if constexpr (MODEL == MODEL_ZGB) {
             if (has_top)
-                store_seg<P>(gtop, load_seg<P>(tile + tb - C::S));
+                gstore_seg<P, COH>(gtop, load_seg<P>(tile + tb - C::S));
             if (has_bot)
-                store_seg<P>(gbot, load_seg<P>(tile + tb + C::S));
+                gstore_seg<P, COH>(gbot, load_seg<P>(tile + tb + C::S));
             if (has_l)
-                grow[xl] = tile[tb - 1];
+                gstore_byte<COH>(grow + xl, tile[tb - 1]);
             if (has_r)
-                grow[xr] = tile[tb + P];
+                gstore_byte<COH>(grow + xr, tile[tb + P]);
         }
     }
     if (lane == 0) {
@@ -685,8 +753,10 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_batched(const JobDesc* __res
 // colour barrier becomes a neighbour-only wait, the local synchronisation of
 // Sec. 2.2 stage 2: before block m runs window w, each block that can
 // interact with it must have finished all its windows before w.  epoch[n] is
-// the next window block n takes part in, published with agent-scope release
-// after its block-window and read with agent-scope acquire.  Same-colour
+// the next window block n takes part in.  The lattice and the epochs are only
+// touched with agent-coherent loads and stores (no whole-cache write-back or
+// invalidation); an epoch is stored after the block's lattice stores have
+// completed and lattice loads are issued after the epoch loads.  Same-colour
 // blocks of one window never interact, windows only depend on earlier ones,
 // so every wait ends; a wait longer than wait_ticks (100 MHz wall clock)
 // raises the abort flag and every wave leaves.
@@ -721,10 +791,18 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_persistent(PersistArgs a)
             }
             if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
                 return;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            block_window<P, BX, BY, MODEL>(a.lat, a.table, a.cnt, a.Lx, a.Ly, m, a.NBX, a.k0, a.k1, (uint32_t)w,
-                                           a.win_dur[w], lds + wid * C::LDS);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            // the lattice is read and written with agent-coherent accesses, so
+            // only their order matters here: loads after the epoch loads,
+            // epoch store after the lattice stores have completed
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            block_window<P, BX, BY, MODEL, true>(a.lat, a.table, a.cnt, a.Lx, a.Ly, m, a.NBX, a.k0, a.k1,
+                                                 (uint32_t)w, a.win_dur[w], lds + wid * C::LDS);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            // a workgroup-scope release does not wait for stores to complete;
+            // the epoch must not be published before the block's agent-scope
+            // lattice stores have been performed (vmcnt(0), other counters
+            // left at their maxima)
+            __builtin_amdgcn_s_waitcnt(0x0F70);
             if (lane == 0)
                 __hip_atomic_store(&a.epoch[m], nxt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }

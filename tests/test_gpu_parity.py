@@ -361,3 +361,27 @@ def test_persistent_full_run_config1(F, orc, ctx):
         p.step_compare_end(40)
     finally:
         F.fskmc_ctx_set_persistent(ctx, 0)
+
+
+@pytest.mark.parametrize("case", [
+    (FLIP, 1024, 1024, (1.0, 1.0, 1.0, 0.0, 1.0), 16, 2, 0.1, 100.0, 0, "bernoulli", 2000, 2000),
+    (FLIP, 1024, 1024, (1.0, 1.0, 0.5, 0.0, 1.0), 16, 2, 0.01, 100.0, 1, "bernoulli", 3000, 1000),
+    (ZGB, 4096, 4096, (0.5, 1000.0, 10.0), 32, 4, 0.05, 10.0, 1, "empty", 280, 70),
+], ids=["config1-full-run", "config1-strang-dt0.01", "config2-280-windows"])
+def test_persistent_equals_per_window_at_scale(F, ctx, case):
+    """Whole runs at the workloads' full sizes: the persistent sweep and one
+    launch per window give identical lattices and event counts."""
+    import hashlib
+    kind, Lx, Ly, prm, b, ncol, dt, T, split, init, nwin, chunk = case
+    out = []
+    for persist in (0, chunk):
+        F.fskmc_ctx_set_persistent(ctx, persist)
+        try:
+            s = F.Sim(ctx, kind, Lx, Ly, prm, b=b, n_colours=ncol, dt=dt, T=T, split=split, seed=0, replica=7)
+            s.init(1 if init == "bernoulli" else 0, 0.5)
+            s.advance(nwin)
+            out.append((hashlib.sha256(s.lattice().tobytes()).hexdigest(), s.observe()["events"]))
+            s.close()
+        finally:
+            F.fskmc_ctx_set_persistent(ctx, 0)
+    assert out[0] == out[1]
