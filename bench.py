@@ -72,14 +72,25 @@ def run_once(F, sim, wl):
     return sim.observe()
 
 
-def roofline(F, ctx, kind, b, obs_list, launches, kernel_name):
+def resident_bytes(b, block_windows, sites, launches):
+    """Algorithmic HBM bytes of the resident sweep: each launch reads and
+    writes its lattice of `sites` bytes once; per block-window four 8-byte
+    edge words are read and four written, and the 16-byte counter record is
+    updated (28 bytes moved)."""
+    return launches * 2 * sites + block_windows * (64 + 28)
+
+
+def roofline(F, ctx, kind, b, obs_list, launches, kernel_name, resident_sites=0):
     """Achieved algorithmic HBM GB/s of the sweep kernel: bytes per launch
     (from the run's block-window and write-back counts) over the average
     duration of the launches bracketed by kernel-side timing events."""
     ms_total, n_timed = F.fskmc_ctx_read_kernel_timing(ctx)
     bw = sum(o["block_windows"] for o in obs_list)
     wr = sum(o["writes"] for o in obs_list)
-    bytes_per_launch = hbm_bytes(kind, b, bw, wr) / max(launches, 1)
+    if resident_sites:
+        bytes_per_launch = resident_bytes(b, bw, resident_sites, launches) / max(launches, 1)
+    else:
+        bytes_per_launch = hbm_bytes(kind, b, bw, wr) / max(launches, 1)
     avg = ms_total / 1e3 / max(n_timed, 1)
     achieved = bytes_per_launch / avg / 1e9 if n_timed else 0.0
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -87,7 +98,7 @@ def roofline(F, ctx, kind, b, obs_list, launches, kernel_name):
             "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg * 1e6, "timed_launches": n_timed}
 
 
-def bench_plain(F, ctx, wl, steps, warmup, stride, persist=0):
+def bench_plain(F, ctx, wl, steps, warmup, stride, persist=0, resident=False):
     sims = [make_sim(F, ctx, wl, replica=i) for i in range(warmup + steps)]
     for i in range(warmup):
         run_once(F, sims[i], wl)
@@ -101,11 +112,13 @@ def bench_plain(F, ctx, wl, steps, warmup, stride, persist=0):
     el = time.perf_counter() - t0
     if persist > 0:
         launches = sum(-(-o["window"] // persist) for o in obs)
-        kname = f"k_sweep_persistent<P={wl['b'] ** 2 // 64},{wl['kind']}> ({persist} windows per launch)"
+        kname = (f"k_sweep_{'resident' if resident else 'persistent'}<P={wl['b'] ** 2 // 64},{wl['kind']}> "
+                 f"({persist} windows per launch)")
     else:
         launches = sum(o["window"] for o in obs)
         kname = f"k_sweep_single<P={wl['b'] ** 2 // 64},{wl['kind']}>"
-    rl = roofline(F, ctx, wl["kind"], wl["b"], obs, launches, kname)
+    rl = roofline(F, ctx, wl["kind"], wl["b"], obs, launches, kname,
+                  resident_sites=wl["Lx"] * wl["Ly"] if resident else 0)
     F.fskmc_ctx_set_kernel_timing(ctx, 0)
     for s in sims:
         s.close()
@@ -242,6 +255,8 @@ def main():
     ap.add_argument("--waves-per-group", type=int, default=2)
     ap.add_argument("--persistent", type=int, default=0,
                     help="windows per persistent launch for single-lattice runs (0: one launch per window)")
+    ap.add_argument("--no-resident", action="store_true",
+                    help="persistent sweeps stream every block from HBM each window instead of keeping it in LDS")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-jobs", type=int, default=512, help="0 skips the batched measurement")
@@ -275,9 +290,11 @@ def main():
     ctx = F.fskmc_ctx_create(0, torch.cuda.current_stream().cuda_stream)
     F.fskmc_ctx_set_waves_per_group(ctx, args.waves_per_group)
     F.fskmc_ctx_set_persistent(ctx, args.persistent)
+    F.fskmc_ctx_set_resident(ctx, not args.no_resident)
     wl = workloads.c1(J=args.J, dt=args.dt, split=args.split)
     log(f"workload {wl['name']}")
-    p = bench_plain(F, ctx, wl, args.steps, args.warmup, args.timing_stride, args.persistent)
+    resident = args.persistent > 0 and not args.no_resident
+    p = bench_plain(F, ctx, wl, args.steps, args.warmup, args.timing_stride, args.persistent, resident)
     log(f"plain: {args.steps} steps, {p['events']} events in {p['seconds']:.3f} s, "
         f"kernel avg {p['roofline']['avg_launch_us']:.2f} us")
     result = {
@@ -296,7 +313,7 @@ def main():
         "config": {"workload": wl["name"], "lattice": [wl["Lx"], wl["Ly"]], "block": [wl["b"], wl["b"]],
                    "colours": wl["n_colours"], "windows_per_step": p["windows"] // args.steps,
                    "events_per_step": p["events"] / args.steps, "waves_per_group": args.waves_per_group,
-                   "persistent_windows_per_launch": args.persistent},
+                   "persistent_windows_per_launch": args.persistent, "resident": resident},
         "roofline": p["roofline"],
     }
     if args.sweep:
@@ -305,7 +322,7 @@ def main():
             for dt in (0.01, 0.1, 1.0):
                 for split in (0, 1):
                     w2 = workloads.c1(J=J, dt=dt, split=split)
-                    q = bench_plain(F, ctx, w2, 1, 1, 0, args.persistent)
+                    q = bench_plain(F, ctx, w2, 1, 1, 0, args.persistent, resident)
                     sweep.append({"workload": w2["name"], "value": q["events"] / q["seconds"],
                                   "ms_per_step": q["seconds"] * 1e3, "events_per_step": q["events"]})
                     log(f"sweep {w2['name']}: {q['events'] / q['seconds']:.3g} events/s")

@@ -207,6 +207,15 @@ int fskmc_ctx_set_waves_per_group(fskmc_ctx* ctx, int waves);
  * returns FSKMC_EDEVICE. */
 int fskmc_ctx_set_persistent(fskmc_ctx* ctx, int windows);
 
+/* Knob that never changes results (default on): persistent sweeps of spin-flip
+ * simulations keep every block in LDS for the whole launch and exchange only
+ * the blocks' one-site boundary layers between windows (Sec. 2.2, local
+ * synchronisation), when the blocks fit the waves resident on the device (at
+ * most four blocks per wave); otherwise, and for the reaction model, the
+ * persistent sweep streams each block from HBM every window.  After a
+ * persistent sweep returns FSKMC_EDEVICE the lattice contents are unspecified. */
+int fskmc_ctx_set_resident(fskmc_ctx* ctx, int on);
+
 /* Measurement aid.  With stride > 0, every stride-th sweep launch on this
  * context is bracketed by two HIP timing events recorded on the context
  * stream (stride 0 turns it off).  read returns the summed duration of the

@@ -86,6 +86,7 @@ struct fskmc_ctx {
     uint64_t timed_n = 0;
     // persistent multi-window sweeps (0 = one launch per window)
     int persist = 0;
+    bool resident = true;        // spin flip: keep blocks in LDS across the windows of a launch
     int32_t* d_abort = nullptr;  // raised by the persistent kernel on a timed-out wait
     int32_t* h_abort = nullptr;  // pinned copy, refreshed after each persistent launch
 };
@@ -124,6 +125,10 @@ struct fskmc_sim {
     int32_t* d_next = nullptr;
     int32_t* d_nbr = nullptr;
     int32_t* d_epoch = nullptr;
+    // resident sweep: last window of each colour before w, tagged edge words
+    std::vector<int32_t> prev_part;  // [n_colours][n_windows+1]
+    int32_t* d_prev = nullptr;
+    unsigned long long* d_edge = nullptr;
 };
 
 namespace {
@@ -341,6 +346,8 @@ void free_sim_device(fskmc_sim* S)
     (void)hipFree(S->d_next);
     (void)hipFree(S->d_nbr);
     (void)hipFree(S->d_epoch);
+    (void)hipFree(S->d_prev);
+    (void)hipFree(S->d_edge);
     S->d_lat = nullptr;
 }
 
@@ -455,6 +462,54 @@ int enqueue_persistent(fskmc_sim* S, uint64_t w0, uint64_t w1)
     a.wait_ticks = 200000000ull; // two seconds of the 100 MHz wall clock
     const LaunchTiming tk = timing_begin(c);
     HIP_TRY(launch_sweep_persistent(S->model, S->P, S->shape, c->wpg, a, S->max_per_colour, st, tk));
+    timing_end(c, tk);
+    HIP_TRY(hipMemcpyAsync(c->h_abort, c->d_abort, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    for (uint64_t w = w0; w < w1; ++w) {
+        const int col = S->win_colour[w];
+        S->block_windows += (uint64_t)(S->colour_off[col + 1] - S->colour_off[col]);
+    }
+    return FSKMC_OK;
+}
+
+// Windows [w0, w1) of a spin-flip simulation in one resident launch: edge
+// tags set to a value no window expects, the abort flag cleared, one
+// cooperative launch.  Returns 1 (nothing enqueued but the fill) when the
+// blocks do not fit the resident waves; the caller then streams.
+int enqueue_resident(fskmc_sim* S, uint64_t w0, uint64_t w1)
+{
+    fskmc_ctx* c = S->ctx;
+    hipStream_t st = c->stream;
+    HIP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(S->d_edge), 4 * (int64_t)S->nb, ~0ull, st));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_abort), 1, 0u, st));
+    ResidentArgs a;
+    a.lat = S->d_lat;
+    a.table = S->d_table;
+    a.cnt = S->d_cnt;
+    a.bcol = S->d_bcol;
+    a.win_colour = S->d_wcol;
+    a.win_dur = S->d_wdur;
+    a.prev_part = S->d_prev;
+    a.edge = S->d_edge;
+    a.abort_flag = c->d_abort;
+    a.Lx = S->lat.Lx;
+    a.Ly = S->lat.Ly;
+    a.NBX = S->NBX;
+    a.NBY = S->NBY;
+    a.nb = S->nb;
+    a.k0 = S->key.seed;
+    a.k1 = S->key.replica;
+    a.n_windows = (int)S->n_windows;
+    a.w0 = (int)w0;
+    a.w1 = (int)w1;
+    a.n_waves = 0;
+    a.wait_ticks = 200000000ull; // two seconds of the 100 MHz wall clock
+    const LaunchTiming tk = timing_begin(c);
+    const hipError_t e = launch_sweep_resident(S->P, S->shape, c->wpg, a, st, tk);
+    if (e == hipErrorInvalidConfiguration) {
+        timing_end(c, LaunchTiming{});
+        return 1;
+    }
+    HIP_TRY(e);
     timing_end(c, tk);
     HIP_TRY(hipMemcpyAsync(c->h_abort, c->d_abort, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     for (uint64_t w = w0; w < w1; ++w) {
@@ -584,6 +639,14 @@ int fskmc_ctx_set_persistent(fskmc_ctx* c, int windows)
     if (windows < 0)
         return fail(FSKMC_EINVAL, "windows must be >= 0");
     c->persist = windows;
+    return FSKMC_OK;
+}
+
+int fskmc_ctx_set_resident(fskmc_ctx* c, int on)
+{
+    if (!c)
+        return fail(FSKMC_EINVAL, "ctx is NULL");
+    c->resident = on != 0;
     return FSKMC_OK;
 }
 
@@ -736,6 +799,10 @@ int fskmc_sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, co
     for (int c = 0; c < S->n_colours; ++c)
         for (int64_t w = (int64_t)S->n_windows - 1; w >= 0; --w)
             S->next_part[c * nw1 + w] = S->win_colour[w] == c ? (int32_t)w : S->next_part[c * nw1 + w + 1];
+    S->prev_part.assign((size_t)S->n_colours * nw1, -1);
+    for (int c = 0; c < S->n_colours; ++c)
+        for (uint64_t w = 0; w < S->n_windows; ++w)
+            S->prev_part[c * nw1 + w + 1] = S->win_colour[w] == c ? (int32_t)w : S->prev_part[c * nw1 + w];
     std::vector<int8_t> bcol(S->cmap.begin(), S->cmap.end());
     std::vector<int32_t> nbr;
     build_neighbours(*S, nbr);
@@ -746,7 +813,8 @@ int fskmc_sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, co
         (rc = dev_alloc(&S->d_coff, S->colour_off.size())) || (rc = dev_alloc(&S->d_wcol, S->n_windows)) ||
         (rc = dev_alloc(&S->d_wdur, S->n_windows)) || (rc = dev_alloc(&S->d_bcol, S->nb)) ||
         (rc = dev_alloc(&S->d_next, S->next_part.size())) || (rc = dev_alloc(&S->d_nbr, nbr.size())) ||
-        (rc = dev_alloc(&S->d_epoch, S->nb))) {
+        (rc = dev_alloc(&S->d_epoch, S->nb)) || (rc = dev_alloc(&S->d_prev, S->prev_part.size())) ||
+        (rc = dev_alloc(&S->d_edge, 4 * (size_t)S->nb))) {
         free_sim_device(S);
         delete S;
         return rc;
@@ -759,6 +827,8 @@ int fskmc_sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, co
         e = hipMemcpyAsync(S->d_next, S->next_part.data(), S->next_part.size() * 4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(S->d_nbr, nbr.data(), nbr.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(S->d_prev, S->prev_part.data(), S->prev_part.size() * 4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(S->d_table, S->table.data(), S->table.size() * 8, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
@@ -862,7 +932,11 @@ int fskmc_sim_advance(fskmc_sim* S, uint64_t n_windows)
         uint64_t left = n_windows;
         while (left > 0) {
             const uint64_t k = std::min<uint64_t>(left, (uint64_t)S->ctx->persist);
-            int rc = enqueue_persistent(S, S->window, S->window + k);
+            int rc = 1;
+            if (S->ctx->resident && S->model == FSKMC_MODEL_FLIP)
+                rc = enqueue_resident(S, S->window, S->window + k);
+            if (rc == 1)
+                rc = enqueue_persistent(S, S->window, S->window + k);
             if (rc)
                 return rc;
             S->window += k;

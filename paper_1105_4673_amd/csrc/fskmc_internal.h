@@ -72,6 +72,27 @@ struct PersistArgs {
     unsigned long long wait_ticks;
 };
 
+// Resident persistent sweep (spin flip): every wave keeps the tiles of the
+// blocks it owns in LDS for the whole launch; neighbouring blocks exchange only
+// their one-site boundary layers through tagged words.
+struct ResidentArgs {
+    uint8_t* lat;
+    const double* table;
+    BlockCount* cnt;
+    const int8_t* bcol;         // [n_blocks]: colour of each block
+    const int8_t* win_colour;   // per window
+    const double* win_dur;      // per window
+    const int32_t* prev_part;   // [n_colours][n_windows+1]: last window < w of colour c, -1 if none
+    unsigned long long* edge;   // [n_blocks][4]: tag | bits << 32 of the first/last row, first/last column
+    int32_t* abort_flag;        // raised by a wave whose wait timed out
+    int Lx, Ly, NBX, NBY, nb;
+    uint32_t k0, k1;
+    int n_windows;
+    int w0, w1;
+    int n_waves;                // set by the launcher
+    unsigned long long wait_ticks;
+};
+
 // Optional kernel-side timing: when both events are set, the launch records
 // them at the kernel's own start and end (hipExtLaunchKernelGGL).
 struct LaunchTiming {
@@ -86,6 +107,9 @@ hipError_t launch_sweep_batched(int model, int P, int shape, int wpg, const JobD
                                 hipStream_t s, LaunchTiming tm);
 hipError_t launch_sweep_persistent(int model, int P, int shape, int wpg, const PersistArgs& a,
                                    int max_blocks_per_colour, hipStream_t s, LaunchTiming tm);
+// hipErrorInvalidConfiguration when the blocks do not fit the resident waves
+// (the caller then uses the streaming persistent sweep).
+hipError_t launch_sweep_resident(int P, int shape, int wpg, const ResidentArgs& a, hipStream_t s, LaunchTiming tm);
 hipError_t launch_epoch_init(int32_t* epoch, const int8_t* bcol, const int32_t* next_part, int nb, int n_windows,
                              int w0, hipStream_t s);
 hipError_t launch_init(uint8_t* lat, int64_t n, int kind, double p, uint32_t k0, uint32_t k1,

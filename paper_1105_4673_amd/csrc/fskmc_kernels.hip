@@ -512,10 +512,12 @@ __device__ __forceinline__ int descend(const Tree<P>& T, double tg, int lane, do
 // (e, m, w, 0); the draw whose time passes the window end is discarded.
 // Spin flip keeps the block in registers during the window and puts it back
 // into the tile at the end; pair events update the tile in place.
-// Returns the number of accepted events.
+// Returns the number of accepted events.  With `pre`, (nl0, v0) are this
+// lane's -log U and V of draw e = lane, computed by the caller ahead of time.
 template <int P, int BX, int BY, int MODEL>
 __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const double* __restrict__ chan, uint32_t m,
-                                               uint32_t w, double dur, uint32_t k0, uint32_t k1)
+                                               uint32_t w, double dur, uint32_t k0, uint32_t k1, bool pre = false,
+                                               double nl0 = 0.0, double v0 = 0.0)
 {
     using C = Cfg<P, BX, BY, MODEL>;
     const int lane = threadIdx.x & 63;
@@ -532,8 +534,8 @@ __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const
 
     double t = 0.0;
     uint32_t e = 0, e0 = 0;
-    double nl_b = 0.0, v_b = 0.0; // this lane's draw e0 + lane: -log U and V
-    bool have_batch = false;
+    double nl_b = nl0, v_b = v0; // this lane's draw e0 + lane: -log U and V
+    bool have_batch = pre;
     for (;;) {
         const double R = uniform_f64(T.R);
         if (R == 0.0)
@@ -809,6 +811,214 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_persistent(PersistArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Resident persistent sweep (spin flip).  Every wave owns up to BPW blocks for
+// the whole launch and keeps their tiles in LDS; the lattice in HBM is read
+// once at the start and written once at the end.  Between windows only the
+// one-site boundary layers move (the local synchronisation of Sec. 2.2 stage
+// 2): after each of its windows a block publishes its first/last row and
+// first/last column as edge[4m + d] = tag | bits << 32 with one 64-bit
+// agent-coherent store, tag = window + 1 (w0 for the state at the start of
+// the launch).  Before block m runs window w it polls the four facing edges
+// of its neighbours until each carries the tag of that neighbour's last
+// window before w; data and tag travel in one single-copy-atomic word, so no
+// fence or completion wait is needed.  A word is overwritten only after every
+// reader of its previous value has published the edges its own window
+// produced, which the writer's next window waits for.  Waits are bounded
+// (wait_ticks of the 100 MHz wall clock; then the abort flag is raised and
+// every wave leaves without writing back).
+
+// The P site states of a lane's segment as bits (site c0 + q in bit q), and back.
+template <int P>
+__device__ __forceinline__ uint32_t seg_bits(const Seg<P>& s)
+{
+    uint32_t b = 0;
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+        b |= ((s.w[q >> 2] >> (8 * (q & 3))) & 1u) << q;
+    return b;
+}
+
+template <int P>
+__device__ __forceinline__ Seg<P> bits_seg(uint32_t b)
+{
+    Seg<P> s;
+#pragma unroll
+    for (int k = 0; k < (P + 3) / 4; ++k)
+        s.w[k] = 0;
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+        s.w[q >> 2] |= ((b >> q) & 1u) << (8 * (q & 3));
+    return s;
+}
+
+// Bits r*LPR + off (r = 0..BY-1) of a ballot, packed into bits r.
+template <int LPR, int BY>
+__device__ __forceinline__ uint32_t ballot_column(uint64_t bal, int off)
+{
+    uint32_t out = 0;
+#pragma unroll
+    for (int r = 0; r < BY; ++r)
+        out |= (uint32_t)((bal >> (r * LPR + off)) & 1u) << r;
+    return out;
+}
+
+// Publish the four boundary layers of the block in `tile` with tag `tag`.
+template <int P, int BX, int BY>
+__device__ __forceinline__ void publish_edges(const uint8_t* tile, int tb, unsigned long long* edge, uint32_t tag,
+                                              int lane, int r, int c0)
+{
+    using C = Cfg<P, BX, BY, MODEL_FLIP>;
+    const uint32_t mask = seg_bits<P>(load_seg<P>(tile + tb));
+    uint32_t e0 = 0, e1 = 0;
+    if constexpr (C::DIM == 2) {
+#pragma unroll
+        for (int j = 0; j < C::LPR; ++j) {
+            e0 |= (uint32_t)__builtin_amdgcn_readlane((int)mask, j) << (j * P);
+            e1 |= (uint32_t)__builtin_amdgcn_readlane((int)mask, (BY - 1) * C::LPR + j) << (j * P);
+        }
+    }
+    const uint64_t bl = __ballot(c0 == 0 && (mask & 1u));
+    const uint64_t br = __ballot(c0 + P == BX && ((mask >> (P - 1)) & 1u));
+    const uint32_t e2 = ballot_column<C::LPR, BY>(bl, 0);
+    const uint32_t e3 = ballot_column<C::LPR, BY>(br, C::LPR - 1);
+    if (lane < 4) {
+        const uint32_t bits = lane == 0 ? e0 : lane == 1 ? e1 : lane == 2 ? e2 : e3;
+        coh_store(edge + lane, (unsigned long long)tag | ((unsigned long long)bits << 32));
+    }
+}
+
+template <int P, int BX, int BY, int WPG, int BPW>
+__global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
+{
+    using C = Cfg<P, BX, BY, MODEL_FLIP>;
+    constexpr int WAVE = (BPW * C::TILE + C::NTAB * 8 + C::XFER + 15) / 16 * 16;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[WPG * WAVE];
+    const int wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    uint8_t* wl = lds + wid * WAVE;
+    double* tab = reinterpret_cast<double*>(wl + BPW * C::TILE);
+    const int gw = (int)xcd_order(blockIdx.x, gridDim.x) * WPG + wid;
+    const int r = lane / C::LPR, c0 = (lane % C::LPR) * P;
+    const int tb = (r + 1) * C::S + P + c0;
+    const size_t sLx = (size_t)a.Lx;
+
+    for (int i = lane; i < C::NTAB; i += 64)
+        tab[i] = a.table[i];
+    int nown = 0;
+    uint32_t cols = 0; // colour of owned block i in byte i
+    for (int i = 0; i < BPW; ++i) {
+        const int m = gw + i * a.n_waves;
+        if (m >= a.nb)
+            break;
+        const int x0 = (m % a.NBX) * BX, y0 = (m / a.NBX) * BY;
+        store_seg<P>(wl + i * C::TILE + tb, load_seg<P>(a.lat + (size_t)(y0 + r) * sLx + x0 + c0));
+        cols |= (uint32_t)(uint8_t)a.bcol[m] << (8 * i);
+        nown = i + 1;
+    }
+    wave_sync();
+#pragma unroll 1
+    for (int i = 0; i < nown; ++i)
+        publish_edges<P, BX, BY>(wl + i * C::TILE, tb, a.edge + 4 * (size_t)(gw + i * a.n_waves), (uint32_t)a.w0,
+                                 lane, r, c0);
+
+    const int nw1 = a.n_windows + 1;
+#pragma unroll 1
+    for (int w = a.w0; w < a.w1; ++w) {
+        const int c = a.win_colour[w];
+#pragma unroll 1
+        for (int i = 0; i < nown; ++i) {
+            if ((int)((cols >> (8 * i)) & 0xffu) != c)
+                continue;
+            const int m = gw + i * a.n_waves;
+            uint8_t* tile = wl + i * C::TILE;
+            const int bi = m % a.NBX, bj = m / a.NBX;
+            // lanes 0..3 poll the facing edge of the block above, below, left, right
+            const bool active = lane < 4 && (C::DIM == 2 || lane >= 2);
+            int nbm = m, dd = 0;
+            if (lane == 0) {
+                nbm = (bj == 0 ? a.NBY - 1 : bj - 1) * a.NBX + bi;
+                dd = 1;
+            } else if (lane == 1) {
+                nbm = (bj + 1 == a.NBY ? 0 : bj + 1) * a.NBX + bi;
+                dd = 0;
+            } else if (lane == 2) {
+                nbm = bj * a.NBX + (bi == 0 ? a.NBX - 1 : bi - 1);
+                dd = 3;
+            } else if (lane == 3) {
+                nbm = bj * a.NBX + (bi + 1 == a.NBX ? 0 : bi + 1);
+                dd = 2;
+            }
+            const unsigned long long* src = a.edge + 4 * (size_t)nbm + dd;
+            unsigned long long v = 0;
+            uint32_t want = 0;
+            if (active) {
+                v = coh_load(src);
+                const int last = a.prev_part[a.bcol[nbm] * nw1 + w];
+                want = last >= a.w0 ? (uint32_t)last + 1u : (uint32_t)a.w0;
+            }
+            // this lane's first draw of the window, computed while the poll is in flight
+            const uint4 rr = philox10(make_uint4((uint32_t)lane, (uint32_t)m, (uint32_t)w, 0u), a.k0, a.k1);
+            const double nl0 = -fs_log(unif_open0(rr));
+            const double v0 = unif_open1(rr);
+            bool bad = false;
+            if (active && (uint32_t)v != want) {
+                const uint64_t t0 = wall_clock64();
+                for (;;) {
+                    __builtin_amdgcn_s_sleep(1);
+                    v = coh_load(src);
+                    if ((uint32_t)v == want)
+                        break;
+                    if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        bad = true;
+                        break;
+                    }
+                    if (wall_clock64() - t0 > a.wait_ticks) {
+                        __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        bad = true;
+                        break;
+                    }
+                }
+            }
+            if (__ballot(bad))
+                return;
+            const uint32_t hv = (uint32_t)(v >> 32);
+            const uint32_t top = (uint32_t)__builtin_amdgcn_readlane((int)hv, 0);
+            const uint32_t bot = (uint32_t)__builtin_amdgcn_readlane((int)hv, 1);
+            const uint32_t lft = (uint32_t)__builtin_amdgcn_readlane((int)hv, 2);
+            const uint32_t rgt = (uint32_t)__builtin_amdgcn_readlane((int)hv, 3);
+            if constexpr (C::DIM == 2) {
+                if (r == 0)
+                    store_seg<P>(tile + tb - C::S, bits_seg<P>(top >> c0));
+                if (r == BY - 1)
+                    store_seg<P>(tile + tb + C::S, bits_seg<P>(bot >> c0));
+            }
+            if (c0 == 0)
+                tile[tb - 1] = (uint8_t)((lft >> r) & 1u);
+            if (c0 + P == BX)
+                tile[tb + P] = (uint8_t)((rgt >> r) & 1u);
+            wave_sync();
+
+            const uint32_t e = ssa_window<P, BX, BY, MODEL_FLIP>(tile, tab, a.table, (uint32_t)m, (uint32_t)w,
+                                                                 a.win_dur[w], a.k0, a.k1, true, nl0, v0);
+            publish_edges<P, BX, BY>(tile, tb, a.edge + 4 * (size_t)m, (uint32_t)w + 1u, lane, r, c0);
+            if (lane == 0) {
+                a.cnt[m].W = e;
+                if (e > 0) {
+                    atomicAdd(&a.cnt[m].writes, 1u);
+                    atomicAdd(&a.cnt[m].events, (unsigned long long)e);
+                }
+            }
+        }
+    }
+#pragma unroll 1
+    for (int i = 0; i < nown; ++i) {
+        const int m = gw + i * a.n_waves;
+        const int x0 = (m % a.NBX) * BX, y0 = (m / a.NBX) * BY;
+        store_seg<P>(a.lat + (size_t)(y0 + r) * sLx + x0 + c0, load_seg<P>(wl + i * C::TILE + tb));
+    }
+}
+
 // epoch[m] = the first window >= w0 that block m takes part in.
 __global__ void k_epoch_init(int32_t* epoch, const int8_t* bcol, const int32_t* next_part, int nb, int n_windows,
                              int w0)
@@ -1028,6 +1238,70 @@ static hipError_t persist_launch(PersistArgs a, int max_blocks_per_colour, hipSt
     if (tm.stop)
         (void)hipEventRecord(tm.stop, s);
     return e;
+}
+
+// Cooperative launch of the resident sweep: one wave per block while the
+// blocks fit the resident waves, up to RES_BPW blocks per wave beyond that.
+constexpr int RES_BPW = 4;
+
+template <int P, int BX, int BY, int WPG>
+static hipError_t resident_launch(ResidentArgs a, hipStream_t s, LaunchTiming tm)
+{
+    auto kern = k_sweep_resident<P, BX, BY, WPG, RES_BPW>;
+    static int resident_groups = 0;
+    if (resident_groups == 0) {
+        int per_cu = 0, dev = 0, cus = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * WPG, 0);
+        if (e != hipSuccess)
+            return e;
+        if ((e = hipGetDevice(&dev)) != hipSuccess ||
+            (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+            return e;
+        resident_groups = per_cu * cus;
+        if (resident_groups <= 0)
+            return hipErrorInvalidConfiguration;
+    }
+    if (a.nb <= 0)
+        return hipErrorInvalidValue;
+    const int want = (a.nb + WPG - 1) / WPG;
+    const int groups = want < resident_groups ? want : resident_groups;
+    a.n_waves = groups * WPG;
+    if ((a.nb + a.n_waves - 1) / a.n_waves > RES_BPW)
+        return hipErrorInvalidConfiguration;
+    void* args[] = {&a};
+    if (tm.start)
+        (void)hipEventRecord(tm.start, s);
+    hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(groups), dim3(64 * WPG),
+                                              args, 0, s);
+    if (tm.stop)
+        (void)hipEventRecord(tm.stop, s);
+    return e;
+}
+
+template <int WPG>
+static hipError_t resident_dispatch(int P, int shape, const ResidentArgs& a, hipStream_t s, LaunchTiming tm)
+{
+    if (shape == SHAPE_SQ) {
+        if (P == 1)
+            return resident_launch<1, 8, 8, WPG>(a, s, tm);
+        if (P == 4)
+            return resident_launch<4, 16, 16, WPG>(a, s, tm);
+        if (P == 16)
+            return resident_launch<16, 32, 32, WPG>(a, s, tm);
+        return hipErrorInvalidValue;
+    }
+    if (P == 1)
+        return resident_launch<1, 64, 1, WPG>(a, s, tm);
+    if (P == 4)
+        return resident_launch<4, 256, 1, WPG>(a, s, tm);
+    if (P == 16)
+        return resident_launch<16, 1024, 1, WPG>(a, s, tm);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep_resident(int P, int shape, int wpg, const ResidentArgs& a, hipStream_t s, LaunchTiming tm)
+{
+    return wpg == 1 ? resident_dispatch<1>(P, shape, a, s, tm) : resident_dispatch<2>(P, shape, a, s, tm);
 }
 
 template <int MODEL, int WPG>

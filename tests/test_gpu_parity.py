@@ -5,6 +5,8 @@ windows (full-size cases), the per-block event counts W of every active block,
 the host-built rate tables, the Bernoulli initial state and the integer
 observables.  Every call goes through the C ABI of libfskmc.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -337,12 +339,19 @@ def test_batch_equals_alone(F, orc, ctx):
     (FLIP, 256, 256, (1.0, 1.0, 2.0, -0.3, 1.0), 32, 2, 1.0, 100.0, "random", "bernoulli", 5),
     (FLIP, 4096, 1, (1.0, 1.0, 1.0, -0.5, 1.0), 256, 2, 1.0, 100.0, "lie", "bernoulli", 9),
     (ZGB, 256, 256, (0.5, 1000.0, 10.0), 32, 4, 0.05, 10.0, "strang", "empty", 11),
-], ids=["flip64-b8", "flip256-b16-strang", "flip256-b32-random", "flip1d-b256", "zgb256-b32"])
-def test_persistent_sweep_bitwise(F, orc, ctx, case):
+    (FLIP, 16, 16, (1.0, 1.0, 1.0, 0.2, 1.0), 8, 2, 0.5, 20.0, "strang", "bernoulli", 6),
+    (FLIP, 128, 1, (1.0, 1.0, 1.5, 0.0, 1.0), 64, 2, 1.0, 50.0, "random", "bernoulli", 13),
+], ids=["flip64-b8", "flip256-b16-strang", "flip256-b32-random", "flip1d-b256", "zgb256-b32", "flip16-b8-2x2",
+        "flip1d-128-b64-two-blocks"])
+@pytest.mark.parametrize("resident", [1, 0], ids=["resident", "streaming"])
+def test_persistent_sweep_bitwise(F, orc, ctx, case, resident):
     """Several windows inside one persistent kernel (neighbour-only waits
-    instead of a launch per window) give the oracle's bits."""
+    instead of a launch per window) give the oracle's bits, with the blocks
+    kept in LDS across windows (spin flip) or streamed from HBM every window;
+    the smallest grids have the same block on both sides of a block."""
     kind, Lx, Ly, prm, b, ncol, dt, T, split, init, chunk = case
     F.fskmc_ctx_set_persistent(ctx, chunk)
+    F.fskmc_ctx_set_resident(ctx, resident)
     try:
         p = Pair(F, orc, ctx, kind, Lx, Ly, prm, b, ncol, dt, T, split, init=init, seed=0, replica=3)
         p.step_compare_end(3 * chunk + 2)
@@ -350,6 +359,29 @@ def test_persistent_sweep_bitwise(F, orc, ctx, case):
         F.fskmc_sync(ctx)
     finally:
         F.fskmc_ctx_set_persistent(ctx, 0)
+        F.fskmc_ctx_set_resident(ctx, 1)
+
+
+@pytest.mark.parametrize("L", [2048, 4096], ids=["2048-four-blocks-per-wave", "4096-streaming-fallback"])
+def test_resident_many_blocks_per_wave(F, ctx, L):
+    """More blocks than resident waves: up to four blocks per wave stay in LDS
+    (2048^2, 16384 blocks of 16x16); beyond that (4096^2) the persistent sweep
+    falls back to streaming.  Both equal one launch per window."""
+    import hashlib
+    out = []
+    for persist in (0, 12):
+        F.fskmc_ctx_set_persistent(ctx, persist)
+        try:
+            s = F.Sim(ctx, FLIP, L, L, (1.0, 1.0, 1.0, 0.0, 1.0), b=16, n_colours=2, dt=0.1, T=100.0, split=0,
+                      seed=0, replica=5)
+            s.init(1, 0.5)
+            s.advance(12)
+            s.advance(12)
+            out.append((hashlib.sha256(s.lattice().tobytes()).hexdigest(), s.observe()["events"]))
+            s.close()
+        finally:
+            F.fskmc_ctx_set_persistent(ctx, 0)
+    assert out[0] == out[1]
 
 
 def test_persistent_full_run_config1(F, orc, ctx):
@@ -385,3 +417,39 @@ def test_persistent_equals_per_window_at_scale(F, ctx, case):
         finally:
             F.fskmc_ctx_set_persistent(ctx, 0)
     assert out[0] == out[1]
+
+
+def _golden_full_runs():
+    import json
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "full_runs.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+_FULL = _golden_full_runs()
+
+
+@pytest.mark.parametrize("name", sorted(_FULL))
+@pytest.mark.parametrize("persist", [0, 1, 2], ids=["per-window", "persistent-resident", "persistent-streaming"])
+def test_full_run_matches_oracle_golden(F, ctx, name, persist):
+    """Whole runs at the workloads' full sizes against the oracle's final
+    lattice hash and event total (stored by tests/golden/make_full_runs.py,
+    which calls only the oracle): one launch per window, and all windows in
+    one persistent launch."""
+    import hashlib
+    g = _FULL[name]
+    p = g["params"]
+    prm = ((p["k_a"], p["k_d"], p["J"], p["h"], p["beta"]) if g["kind"] == "flip" else (p["y"], p["k_r"], p["D"]))
+    F.fskmc_ctx_set_persistent(ctx, g["windows"] if persist else 0)
+    F.fskmc_ctx_set_resident(ctx, persist != 2)
+    try:
+        s = F.Sim(ctx, g["kind"], g["L"], g["L"], prm, b=g["b"], n_colours=g["n_colours"], dt=g["dt"], T=g["T"],
+                  split=g["split"], seed=g["seed"], replica=g["replica"])
+        s.init(1 if g["init"] == "bernoulli" else 0, 0.5)
+        s.advance(g["windows"])
+        got = (hashlib.sha256(s.lattice().tobytes()).hexdigest(), s.observe()["events"])
+        s.close()
+    finally:
+        F.fskmc_ctx_set_persistent(ctx, 0)
+        F.fskmc_ctx_set_resident(ctx, 1)
+    assert got == (g["sha256"], g["events"])
