@@ -12,15 +12,16 @@
 //     indexed by the site's neighbourhood;
 //   * the canonical heap sum tree over the leaves (row-major leaf order,
 //     node = left + right) lives in registers: each lane holds the pairwise
-//     tree of its P consecutive leaves; the next four levels are a butterfly
-//     inside each 16-lane row built with DPP lane moves (quad_perm,
-//     row_half_mirror, row_mirror), and the two top levels are four uniform
-//     values read with readlane.  Since a + b == b + a in IEEE arithmetic,
-//     every lane holds exactly the node values of the heap tree;
-//   * the descent takes the two top levels uniformly, then all 16 lanes of
-//     the chosen row check at once whether the path of their own subtree is
-//     the one the serial descent takes; a ballot picks the single consistent
-//     lane, which finishes the last log2(P) levels in registers;
+//     tree of its P consecutive leaves; for the next four levels every lane
+//     holds the left and right child sums of its group, fetched with DPP lane
+//     moves inside each 16-lane row (quad_perm, and row shifts restricted to
+//     the banks that need them), and the two top levels are the row and half
+//     sums.  Since a + b == b + a in IEEE arithmetic, every lane holds
+//     exactly the node values of the heap tree;
+//   * the descent runs on all 64 lanes at once: each lane follows the path
+//     of its own lane bits, applies the serial rule with its node's child
+//     sums and stays in a 64-bit ballot mask while every decision agrees; the
+//     single consistent lane finishes the last log2(P) levels in registers;
 //   * the Philox4x32-10 draws and their logarithms are computed 64 at a time,
 //     one per lane, and broadcast with readlane as events consume them.
 //
@@ -130,9 +131,8 @@ __device__ __forceinline__ double uniform_f64(double v)
     return __longlong_as_double(((long long)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-// Value of a double in another lane through a DPP lane move (CTRL is the
-// gfx9 DPP control: 0xB1 = quad_perm [1,0,3,2], 0x4E = quad_perm [2,3,0,1],
-// 0x141 = row_half_mirror, 0x140 = row_mirror).
+// Value of a double in another lane through a DPP lane move that writes every
+// lane (CTRL is the gfx9 DPP control, e.g. quad_perm 0x00-0xFF).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v)
 {
@@ -270,68 +270,142 @@ struct Cfg {
 };
 
 // The block's sum tree.  Per lane: lv = pairwise tree of its P leaves
-// (lv[1] lane sum, lv[P+q] leaf q); g[s] (s = 0..4) = sum of the aligned
-// group of 2^s lanes containing the lane, pr[s] (s = 0..3) = that of the
-// sibling group.  Uniform: q4[k] = sum of lanes [16k, 16k+16), h5[k] = sum of
-// lanes [32k, 32k+32), R = root.
+// (lv[1] lane sum, lv[P+q] leaf q).  Level s = 0..3 of a 16-lane row: L[s]
+// and Rt[s] = the sums of the left and right halves of the aligned group of
+// 2^(s+1) lanes that contains the lane; level 4: L4 / Rt4 = the two row sums
+// of the lane's 32-lane half; level 5: h0 / h1 = the two half sums; R = root.
+// Every value is the heap tree's node (node = left + right, which is the same
+// IEEE result in either operand order).
 template <int P>
 struct Tree {
     double lv[2 * P];
-    double g[5], pr[4];
-    double q4[4], h5[2], R;
+    double L[4], Rt[4];
+    double L4, Rt4, h0, h1, R;
 };
 
-// Butterfly inside each 16-lane row: from x (this lane's value) g[s] = sum of
-// the aligned 2^s-lane group, pr[s] = sum of its sibling group, s = 0..3, and
-// g[4] = the row's sum.  DPP moves pick any lane of the sibling group; all
-// lanes of a group hold the same bits because IEEE addition commutes.
-__device__ __forceinline__ void row_butterfly(double x, double (&g)[5], double (&pr)[4])
+// DPP lane move of a double: lanes enabled by BANK (4-lane banks of each
+// 16-lane row) take the value from the lane CTRL selects, the others keep
+// `old`.  CTRL (gfx9): quad_perm 0x00-0xFF, row_shl:n 0x100+n, row_shr:n
+// 0x110+n.
+template <int CTRL, int BANK>
+__device__ __forceinline__ double dpp_keep_f64(double old, double v)
 {
-    g[0] = x;
-    pr[0] = dpp_f64<0xB1>(g[0]);
-    g[1] = g[0] + pr[0];
-    pr[1] = dpp_f64<0x4E>(g[1]);
-    g[2] = g[1] + pr[1];
-    pr[2] = dpp_f64<0x141>(g[2]);
-    g[3] = g[2] + pr[2];
-    pr[3] = dpp_f64<0x140>(g[3]);
-    g[4] = g[3] + pr[3];
+    const long long b = __double_as_longlong(v), o = __double_as_longlong(old);
+    const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)b, CTRL, 0xF, BANK, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(b >> 32), CTRL, 0xF, BANK, false);
+    return __longlong_as_double(((long long)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-// Four descent levels inside a 16-lane row whose subtree sums are (g, pr):
-// each lane follows its own root-to-leaf path and stays `ok` while every
-// decision agrees with its lane bits.  Returns the residual target.
-__device__ __forceinline__ double row_descend(const double (&g)[5], const double (&pr)[4], double tl, int lane,
-                                              bool& ok)
+// The four levels of a 16-lane row from x (this lane's subtree sum): the left
+// and right child sums of every lane's group at each level, fetched with DPP
+// from the lane of the left (right) group, or kept where the lane is in that
+// group.  Returns the row's sum.
+__device__ __forceinline__ double row_tree(double x, double (&L)[4], double (&Rt)[4])
 {
-#pragma unroll
-    for (int s = 3; s >= 0; --s) {
-        const bool bit = (lane >> s) & 1;
-        const double left = bit ? pr[s] : g[s];
-        const double right = bit ? g[s] : pr[s];
-        const bool go_right = !(tl < left || right == 0.0);
-        ok = ok && (go_right == bit);
-        if (go_right)
-            tl = tl - left;
-    }
+    L[0] = dpp_f64<0xA0>(x);  // quad_perm [0,0,2,2]
+    Rt[0] = dpp_f64<0xF5>(x); // quad_perm [1,1,3,3]
+    x = L[0] + Rt[0];
+    L[1] = dpp_f64<0x44>(x);  // quad_perm [0,1,0,1]
+    Rt[1] = dpp_f64<0xEE>(x); // quad_perm [2,3,2,3]
+    x = L[1] + Rt[1];
+    L[2] = dpp_keep_f64<0x114, 0xA>(x, x); // row_shr:4 into banks 1, 3
+    Rt[2] = dpp_keep_f64<0x104, 0x5>(x, x); // row_shl:4 into banks 0, 2
+    x = L[2] + Rt[2];
+    L[3] = dpp_keep_f64<0x118, 0xC>(x, x); // row_shr:8 into banks 2, 3
+    Rt[3] = dpp_keep_f64<0x108, 0x3>(x, x); // row_shl:8 into banks 0, 1
+    return L[3] + Rt[3];
+}
+
+// Lanes whose bit S is set (the lanes whose path goes right at level S).
+template <int S>
+__device__ __forceinline__ constexpr uint64_t lanes_right()
+{
+    uint64_t m = 0;
+    for (int l = 0; l < 64; ++l)
+        if ((l >> S) & 1)
+            m |= 1ull << l;
+    return m;
+}
+
+// One level of the lane-parallel descent: every lane follows the path given
+// by its own lane bits, with (left, right) the child sums of its node at this
+// level.  The serial rule (go right iff not (tg < left or right == 0)) must
+// agree with the lane's bit S for the lane to stay in `ok`.  The residual is
+// fma(-left, bitf, tl) with bitf = 1.0 on paths that go right and 0.0 on the
+// others: the product is exact, so this is tl - left rounded once, or tl.
+template <int S>
+__device__ __forceinline__ void path_level(double& tl, uint64_t& ok, int lane, double left, double right)
+{
+    const uint64_t not_below = __builtin_amdgcn_ballot_w64(!(tl < left));
+    const uint64_t nonzero = __builtin_amdgcn_ballot_w64(right != 0.0);
+    const uint64_t right_taken = not_below & nonzero;
+    ok &= ~(right_taken ^ lanes_right<S>());
+    tl = __builtin_fma(-left, ((lane >> S) & 1) ? 1.0 : 0.0, tl);
+}
+
+// Four descent levels inside a 16-lane row (row_tree's L, Rt).
+__device__ __forceinline__ double row_descend(const double (&L)[4], const double (&Rt)[4], double tl, int lane,
+                                              uint64_t& ok)
+{
+    path_level<3>(tl, ok, lane, L[3], Rt[3]);
+    path_level<2>(tl, ok, lane, L[2], Rt[2]);
+    path_level<1>(tl, ok, lane, L[1], Rt[1]);
+    path_level<0>(tl, ok, lane, L[0], Rt[0]);
     return tl;
 }
 
-// In-lane pairwise levels, the row butterfly and the two top levels, from
-// the leaves in T.lv[P..2P).
+// Cross-row moves of a double with v_permlane16_swap / v_permlane32_swap
+// (ROWS = 16 or 32), both operands the same value: `lo` receives the value of
+// the lower row (half) of each pair in both, `hi` that of the upper.
+constexpr bool kTopPermlane = true;
+
+template <int ROWS>
+__device__ __forceinline__ void swap_f64(double v, double& lo, double& hi)
+{
+    const long long b = __double_as_longlong(v);
+    const unsigned l = (unsigned)(uint32_t)b, h = (unsigned)(uint32_t)(b >> 32);
+    unsigned a0, a1, c0, c1;
+    if constexpr (ROWS == 16) {
+        const auto rl = __builtin_amdgcn_permlane16_swap(l, l, false, false);
+        const auto rh = __builtin_amdgcn_permlane16_swap(h, h, false, false);
+        a0 = rl[0]; a1 = rl[1]; c0 = rh[0]; c1 = rh[1];
+    } else {
+        const auto rl = __builtin_amdgcn_permlane32_swap(l, l, false, false);
+        const auto rh = __builtin_amdgcn_permlane32_swap(h, h, false, false);
+        a0 = rl[0]; a1 = rl[1]; c0 = rh[0]; c1 = rh[1];
+    }
+    lo = __longlong_as_double(((long long)c0 << 32) | a0);
+    hi = __longlong_as_double(((long long)c1 << 32) | a1);
+}
+
+// In-lane pairwise levels, the row levels and the two top levels, from the
+// leaves in T.lv[P..2P).
 template <int P>
 __device__ __forceinline__ void finish_tree(Tree<P>& T)
 {
 #pragma unroll
     for (int k = P - 1; k >= 1; --k)
         T.lv[k] = T.lv[2 * k] + T.lv[2 * k + 1];
-    row_butterfly(T.lv[1], T.g, T.pr);
+    const double row = row_tree(T.lv[1], T.L, T.Rt);
+    if constexpr (kTopPermlane) {
+        // v_permlane16_swap with both operands = the row sums: the first
+        // result holds the even row of each row pair in both rows, the second
+        // the odd row; v_permlane32_swap does the same for the two halves
+        swap_f64<16>(row, T.L4, T.Rt4);
+        const double half = T.L4 + T.Rt4;
+        swap_f64<32>(half, T.h0, T.h1);
+    } else {
+        double q4[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-        T.q4[k] = readlane_f64(T.g[4], 16 * k);
-    T.h5[0] = T.q4[0] + T.q4[1];
-    T.h5[1] = T.q4[2] + T.q4[3];
-    T.R = T.h5[0] + T.h5[1];
+        for (int k = 0; k < 4; ++k)
+            q4[k] = readlane_f64(row, 16 * k);
+        T.h0 = q4[0] + q4[1];
+        T.h1 = q4[2] + q4[3];
+        const bool upper = (threadIdx.x & 32) != 0;
+        T.L4 = upper ? q4[2] : q4[0];
+        T.Rt4 = upper ? q4[3] : q4[1];
+    }
+    T.R = T.h0 + T.h1;
 }
 
 // Leaves from the LDS tile: the table entry of each site's neighbourhood
@@ -406,29 +480,33 @@ __device__ __forceinline__ void flip_sites_from_tile(const uint8_t* tile, int tb
     }
 }
 
+// Flip of block site (xi, yi) (uniform) to state v: toggle it and add +-1 to
+// the counts of its in-block neighbours.  Site g of the block lives in lane
+// g / P, byte g % P (row-major, P consecutive sites per lane), so each
+// affected byte is one lane compare against a scalar site index.
 template <int P>
-__device__ __forceinline__ uint32_t byte_bit(int d)
+__device__ __forceinline__ uint32_t site_byte(int lane, int g, int k)
 {
-    constexpr unsigned lim = P < 4 ? P : 4;
-    return (unsigned)d < lim ? 1u << (8 * d) : 0u;
+    // bit 0 of site g's byte if g (>= 0) is held in word k of this lane
+    const int q = g % P; // position within the lane's P sites
+    const bool mine = g >= 0 && (q >> 2) == k && lane == g / P;
+    return mine ? 1u << (8 * (q & 3)) : 0u;
 }
 
-// Flip of block site (xi, yi) to state v: toggle it and add +-1 to the counts
-// of its in-block neighbours.  Lane geometry: row r, columns c0 .. c0+P-1.
-template <int P>
-__device__ __forceinline__ void flip_apply(FlipSites<P>& F, int r, int c0, int xi, int yi, bool v)
+template <int P, int BX, int BY>
+__device__ __forceinline__ void flip_apply(FlipSites<P>& F, int lane, int xi, int yi, bool v)
 {
     constexpr int W = (P + 3) / 4;
-    const int far = -1000;
-    const int p_self = r == yi ? xi - c0 : far;
-    const int p_l = r == yi ? xi - 1 - c0 : far;
-    const int p_r = r == yi ? xi + 1 - c0 : far;
-    const int p_v = (r == yi - 1 || r == yi + 1) ? xi - c0 : far;
+    const int f = yi * BX + xi;
+    const int nl = xi > 0 ? f - 1 : -1;
+    const int nr = xi < BX - 1 ? f + 1 : -1;
+    const int nu = (BY > 1 && yi > 0) ? f - BX : -1;
+    const int nd = (BY > 1 && yi < BY - 1) ? f + BX : -1;
 #pragma unroll
     for (int k = 0; k < W; ++k) {
-        const uint32_t sm = byte_bit<P>(p_self - 4 * k);
-        const uint32_t nm = byte_bit<P>(p_l - 4 * k) | byte_bit<P>(p_r - 4 * k) | byte_bit<P>(p_v - 4 * k);
-        F.s[k] ^= sm;
+        F.s[k] ^= site_byte<P>(lane, f, k);
+        const uint32_t nm =
+            site_byte<P>(lane, nl, k) | site_byte<P>(lane, nr, k) | site_byte<P>(lane, nu, k) | site_byte<P>(lane, nd, k);
         F.n[k] = v ? F.n[k] + nm : F.n[k] - nm;
     }
 }
@@ -436,12 +514,14 @@ __device__ __forceinline__ void flip_apply(FlipSites<P>& F, int r, int c0, int x
 template <int P, int Z>
 __device__ __forceinline__ void flip_leaves(const FlipSites<P>& F, const double* tab, Tree<P>& T)
 {
+    // table index s (z+1) + n of four sites at once (bytes <= 2z+1: no carries)
+    uint32_t idx[(P + 3) / 4];
 #pragma unroll
-    for (int q = 0; q < P; ++q) {
-        const uint32_t s = (F.s[q >> 2] >> (8 * (q & 3))) & 0xffu;
-        const uint32_t n = (F.n[q >> 2] >> (8 * (q & 3))) & 0xffu;
-        T.lv[P + q] = tab[s * (Z + 1) + n];
-    }
+    for (int k = 0; k < (P + 3) / 4; ++k)
+        idx[k] = F.s[k] * (uint32_t)(Z + 1) + F.n[k];
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+        T.lv[P + q] = tab[(idx[q >> 2] >> (8 * (q & 3))) & 0xffu];
     finish_tree(T);
 }
 
@@ -452,20 +532,12 @@ __device__ __forceinline__ void flip_leaves(const FlipSites<P>& F, const double*
 template <int P>
 __device__ __forceinline__ int descend(const Tree<P>& T, double tg, int lane, double* tg_out, double* xfer)
 {
-    // two top levels, uniform
-    bool r = !(tg < T.h5[0] || T.h5[1] == 0.0);
-    if (r)
-        tg = tg - T.h5[0];
-    const int half = r ? 1 : 0;
-    const double L1 = half ? T.q4[2] : T.q4[0];
-    const double R1 = half ? T.q4[3] : T.q4[1];
-    r = !(tg < L1 || R1 == 0.0);
-    if (r)
-        tg = tg - L1;
-    const int quarter = 2 * half + (r ? 1 : 0);
-    // four levels inside the chosen 16-lane row
-    bool ok = (lane >> 4) == quarter;
-    double tl = row_descend(T.g, T.pr, tg, lane, ok);
+    // six levels down to the lane, every lane on its own path
+    uint64_t ok = ~0ull;
+    double tl = tg;
+    path_level<5>(tl, ok, lane, T.h0, T.h1);
+    path_level<4>(tl, ok, lane, T.L4, T.Rt4);
+    tl = row_descend(T.L, T.Rt, tl, lane, ok);
     int q = 0;
     if constexpr (P == 4) {
         // two levels inside the lane, in registers (constant indices only)
@@ -479,8 +551,7 @@ __device__ __forceinline__ int descend(const Tree<P>& T, double tg, int lane, do
             tl = tl - L;
         q = 2 * (gr ? 1 : 0) + (gr2 ? 1 : 0);
     }
-    const uint64_t bal = __ballot(ok);
-    const int js = (__ffsll((unsigned long long)bal) - 1) & 63;
+    const int js = (__ffsll((unsigned long long)ok) - 1) & 63;
     if constexpr (P == 16) {
         // the lane's 16 leaves go to lanes 0..15 through LDS, which rebuild
         // the four in-lane levels with the same row butterfly and descend
@@ -491,12 +562,11 @@ __device__ __forceinline__ int descend(const Tree<P>& T, double tg, int lane, do
                 xfer[i] = T.lv[16 + i];
         }
         wave_sync();
-        double g2[5], pr2[4];
-        row_butterfly(xfer[lane & 15], g2, pr2);
-        bool ok2 = lane < 16;
-        const double t2 = row_descend(g2, pr2, tu, lane, ok2);
-        const uint64_t bal2 = __ballot(ok2);
-        q = (__ffsll((unsigned long long)bal2) - 1) & 15;
+        double L2[4], R2[4];
+        row_tree(xfer[lane & 15], L2, R2);
+        uint64_t ok2 = 0xFFFFull; // lanes 0..15 hold the 16 leaves
+        const double t2 = row_descend(L2, R2, tu, lane, ok2);
+        q = (__ffsll((unsigned long long)ok2) - 1) & 15;
         *tg_out = readlane_f64(t2, q);
         wave_sync();
         return js * P + q;
@@ -566,7 +636,7 @@ __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const
                 word = (q >> 2) == kw ? wv : word;
             }
             const bool was = (word >> (8 * (q & 3))) & 1u;
-            flip_apply<P>(F, r, c0, lx, ly, !was);
+            flip_apply<P, BX, BY>(F, lane, lx, ly, !was);
             flip_leaves<P, C::Z>(F, tab, T);
         } else {
             const int ts = (ly + 1) * C::S + P + lx;
