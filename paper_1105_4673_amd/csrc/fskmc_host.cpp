@@ -502,6 +502,7 @@ int enqueue_resident(fskmc_sim* S, uint64_t w0, uint64_t w1)
     a.w0 = (int)w0;
     a.w1 = (int)w1;
     a.n_waves = 0;
+    a.bpw = 0;
     a.wait_ticks = 200000000ull; // two seconds of the 100 MHz wall clock
     const LaunchTiming tk = timing_begin(c);
     const hipError_t e = launch_sweep_resident(S->P, S->shape, c->wpg, a, st, tk);

@@ -90,6 +90,7 @@ struct ResidentArgs {
     int n_windows;
     int w0, w1;
     int n_waves;                // set by the launcher
+    int bpw;                    // blocks per wave, set by the launcher
     unsigned long long wait_ticks;
 };
 

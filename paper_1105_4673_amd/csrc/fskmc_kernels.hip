@@ -882,9 +882,11 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_persistent(PersistArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Resident persistent sweep (spin flip).  Every wave owns up to BPW blocks for
-// the whole launch and keeps their tiles in LDS; the lattice in HBM is read
-// once at the start and written once at the end.  Between windows only the
+// Resident persistent sweep (spin flip).  Wave g owns blocks g*bpw .. g*bpw +
+// bpw-1 (bpw <= BPW; with bpw = 2 a horizontally adjacent pair, one block of
+// each checkerboard colour, so the wave works in every window) for the whole
+// launch and keeps their tiles in LDS; the lattice in HBM is read once at the
+// start and written once at the end.  Between windows only the
 // one-site boundary layers move (the local synchronisation of Sec. 2.2 stage
 // 2): after each of its windows a block publishes its first/last row and
 // first/last column as edge[4m + d] = tag | bits << 32 with one 64-bit
@@ -894,7 +896,8 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_persistent(PersistArgs a)
 // window before w; data and tag travel in one single-copy-atomic word, so no
 // fence or completion wait is needed.  A word is overwritten only after every
 // reader of its previous value has published the edges its own window
-// produced, which the writer's next window waits for.  Waits are bounded
+// produced, which the writer's next window waits for.  Edges of blocks the
+// same wave owns are read from the wave's LDS copy instead.  Waits are bounded
 // (wait_ticks of the 100 MHz wall clock; then the abort flag is raised and
 // every wave leaves without writing back).
 
@@ -935,8 +938,8 @@ __device__ __forceinline__ uint32_t ballot_column(uint64_t bal, int off)
 
 // Publish the four boundary layers of the block in `tile` with tag `tag`.
 template <int P, int BX, int BY>
-__device__ __forceinline__ void publish_edges(const uint8_t* tile, int tb, unsigned long long* edge, uint32_t tag,
-                                              int lane, int r, int c0)
+__device__ __forceinline__ void publish_edges(const uint8_t* tile, int tb, unsigned long long* edge, uint32_t* ledge,
+                                              uint32_t tag, int lane, int r, int c0)
 {
     using C = Cfg<P, BX, BY, MODEL_FLIP>;
     const uint32_t mask = seg_bits<P>(load_seg<P>(tile + tb));
@@ -955,6 +958,7 @@ __device__ __forceinline__ void publish_edges(const uint8_t* tile, int tb, unsig
     if (lane < 4) {
         const uint32_t bits = lane == 0 ? e0 : lane == 1 ? e1 : lane == 2 ? e2 : e3;
         coh_store(edge + lane, (unsigned long long)tag | ((unsigned long long)bits << 32));
+        ledge[lane] = bits;
     }
 }
 
@@ -962,13 +966,15 @@ template <int P, int BX, int BY, int WPG, int BPW>
 __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
 {
     using C = Cfg<P, BX, BY, MODEL_FLIP>;
-    constexpr int WAVE = (BPW * C::TILE + C::NTAB * 8 + C::XFER + 15) / 16 * 16;
+    constexpr int WAVE = (BPW * C::TILE + C::NTAB * 8 + C::XFER + BPW * 16 + 15) / 16 * 16;
     __shared__ __attribute__((aligned(16))) uint8_t lds[WPG * WAVE];
     const int wid = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     uint8_t* wl = lds + wid * WAVE;
     double* tab = reinterpret_cast<double*>(wl + BPW * C::TILE);
+    uint32_t* ledge = reinterpret_cast<uint32_t*>(wl + BPW * C::TILE + C::NTAB * 8 + C::XFER); // [BPW][4]
     const int gw = (int)xcd_order(blockIdx.x, gridDim.x) * WPG + wid;
+    const int m0 = gw * a.bpw;
     const int r = lane / C::LPR, c0 = (lane % C::LPR) * P;
     const int tb = (r + 1) * C::S + P + c0;
     const size_t sLx = (size_t)a.Lx;
@@ -977,8 +983,8 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
         tab[i] = a.table[i];
     int nown = 0;
     uint32_t cols = 0; // colour of owned block i in byte i
-    for (int i = 0; i < BPW; ++i) {
-        const int m = gw + i * a.n_waves;
+    for (int i = 0; i < a.bpw; ++i) {
+        const int m = m0 + i;
         if (m >= a.nb)
             break;
         const int x0 = (m % a.NBX) * BX, y0 = (m / a.NBX) * BY;
@@ -989,8 +995,8 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
     wave_sync();
 #pragma unroll 1
     for (int i = 0; i < nown; ++i)
-        publish_edges<P, BX, BY>(wl + i * C::TILE, tb, a.edge + 4 * (size_t)(gw + i * a.n_waves), (uint32_t)a.w0,
-                                 lane, r, c0);
+        publish_edges<P, BX, BY>(wl + i * C::TILE, tb, a.edge + 4 * (size_t)(m0 + i), ledge + 4 * i,
+                                 (uint32_t)a.w0, lane, r, c0);
 
     const int nw1 = a.n_windows + 1;
 #pragma unroll 1
@@ -1000,7 +1006,7 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
         for (int i = 0; i < nown; ++i) {
             if ((int)((cols >> (8 * i)) & 0xffu) != c)
                 continue;
-            const int m = gw + i * a.n_waves;
+            const int m = m0 + i;
             uint8_t* tile = wl + i * C::TILE;
             const int bi = m % a.NBX, bj = m / a.NBX;
             // lanes 0..3 poll the facing edge of the block above, below, left, right
@@ -1020,33 +1026,40 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
                 dd = 2;
             }
             const unsigned long long* src = a.edge + 4 * (size_t)nbm + dd;
+            const bool local = nbm >= m0 && nbm < m0 + nown; // owned by this wave: LDS copy
             unsigned long long v = 0;
             uint32_t want = 0;
             if (active) {
-                v = coh_load(src);
-                const int last = a.prev_part[a.bcol[nbm] * nw1 + w];
-                want = last >= a.w0 ? (uint32_t)last + 1u : (uint32_t)a.w0;
+                if (local) {
+                    v = (unsigned long long)ledge[4 * (nbm - m0) + dd] << 32;
+                } else {
+                    v = coh_load(src);
+                    const int last = a.prev_part[a.bcol[nbm] * nw1 + w];
+                    want = last >= a.w0 ? (uint32_t)last + 1u : (uint32_t)a.w0;
+                }
             }
             // this lane's first draw of the window, computed while the poll is in flight
             const uint4 rr = philox10(make_uint4((uint32_t)lane, (uint32_t)m, (uint32_t)w, 0u), a.k0, a.k1);
             const double nl0 = -fs_log(unif_open0(rr));
             const double v0 = unif_open1(rr);
             bool bad = false;
-            if (active && (uint32_t)v != want) {
+            if (active && !local && (uint32_t)v != want) {
                 const uint64_t t0 = wall_clock64();
-                for (;;) {
+                for (uint32_t n = 1;; ++n) {
                     __builtin_amdgcn_s_sleep(1);
                     v = coh_load(src);
                     if ((uint32_t)v == want)
                         break;
-                    if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                        bad = true;
-                        break;
-                    }
-                    if (wall_clock64() - t0 > a.wait_ticks) {
-                        __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        bad = true;
-                        break;
+                    if ((n & 7u) == 0) { // the abort flag and the clock every eighth poll
+                        if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                            bad = true;
+                            break;
+                        }
+                        if (wall_clock64() - t0 > a.wait_ticks) {
+                            __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            bad = true;
+                            break;
+                        }
                     }
                 }
             }
@@ -1071,7 +1084,7 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
 
             const uint32_t e = ssa_window<P, BX, BY, MODEL_FLIP>(tile, tab, a.table, (uint32_t)m, (uint32_t)w,
                                                                  a.win_dur[w], a.k0, a.k1, true, nl0, v0);
-            publish_edges<P, BX, BY>(tile, tb, a.edge + 4 * (size_t)m, (uint32_t)w + 1u, lane, r, c0);
+            publish_edges<P, BX, BY>(tile, tb, a.edge + 4 * (size_t)m, ledge + 4 * i, (uint32_t)w + 1u, lane, r, c0);
             if (lane == 0) {
                 a.cnt[m].W = e;
                 if (e > 0) {
@@ -1083,7 +1096,7 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
     }
 #pragma unroll 1
     for (int i = 0; i < nown; ++i) {
-        const int m = gw + i * a.n_waves;
+        const int m = m0 + i;
         const int x0 = (m % a.NBX) * BX, y0 = (m / a.NBX) * BY;
         store_seg<P>(a.lat + (size_t)(y0 + r) * sLx + x0 + c0, load_seg<P>(wl + i * C::TILE + tb));
     }
@@ -1333,11 +1346,18 @@ static hipError_t resident_launch(ResidentArgs a, hipStream_t s, LaunchTiming tm
     }
     if (a.nb <= 0)
         return hipErrorInvalidValue;
-    const int want = (a.nb + WPG - 1) / WPG;
-    const int groups = want < resident_groups ? want : resident_groups;
-    a.n_waves = groups * WPG;
-    if ((a.nb + a.n_waves - 1) / a.n_waves > RES_BPW)
+    // two blocks per wave (an adjacent pair of the two colours), more when the
+    // lattice has more blocks than twice the resident waves
+    const int cap = resident_groups * WPG;
+    int bpw = a.nb >= 2 ? 2 : 1;
+    if (bpw * cap < a.nb)
+        bpw = (a.nb + cap - 1) / cap;
+    if (bpw > RES_BPW)
         return hipErrorInvalidConfiguration;
+    a.bpw = bpw;
+    const int waves = (a.nb + bpw - 1) / bpw;
+    const int groups = (waves + WPG - 1) / WPG;
+    a.n_waves = groups * WPG;
     void* args[] = {&a};
     if (tm.start)
         (void)hipEventRecord(tm.start, s);
