@@ -82,7 +82,25 @@ def resident_bytes(b, block_windows, sites, launches):
     return launches * 2 * sites + block_windows * (64 + 28)
 
 
-def roofline(F, ctx, kind, b, obs_list, launches, kernel_name, resident_sites=0):
+def measured_traffic(symbol):
+    """HBM bytes per launch of `symbol` from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes recorded in profiles/hbm_traffic.json (scaled by the
+    copy calibration), or None when there is no record or the kernel source
+    has changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "hbm_traffic.json")) as f:
+            rec = json.load(f)["kernels"].get(symbol)
+        with open(os.path.join(ROOT, "paper_1105_4673_amd", "csrc", "fskmc_kernels.hip"), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError, KeyError):
+        return None, None
+    if not rec or rec.get("kernel_source_sha256") != sha:
+        return None, None
+    return rec["traffic_bytes_per_launch"], rec["source"]
+
+
+def roofline(F, ctx, kind, b, obs_list, launches, kernel_name, resident_sites=0, symbol=None):
     """Achieved algorithmic HBM GB/s of the sweep kernel: bytes per launch
     (from the run's block-window and write-back counts) over the average
     duration of the launches bracketed by kernel-side timing events."""
@@ -95,12 +113,13 @@ def roofline(F, ctx, kind, b, obs_list, launches, kernel_name, resident_sites=0)
         bytes_per_launch = hbm_bytes(kind, b, bw, wr) / max(launches, 1)
     avg = ms_total / 1e3 / max(n_timed, 1)
     achieved = bytes_per_launch / avg / 1e9 if n_timed else 0.0
+    traffic, source = measured_traffic(symbol)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel_name,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": source, "kernel": kernel_name,
             "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg * 1e6, "timed_launches": n_timed}
 
 
-def bench_plain(F, ctx, wl, steps, warmup, stride, persist=0, resident=False):
+def bench_plain(F, ctx, wl, steps, warmup, stride, persist=0, resident=False, wpg=2):
     sims = [make_sim(F, ctx, wl, replica=i) for i in range(warmup + steps)]
     for i in range(warmup):
         run_once(F, sims[i], wl)
@@ -112,15 +131,18 @@ def bench_plain(F, ctx, wl, steps, warmup, stride, persist=0, resident=False):
     obs = [run_once(F, sims[warmup + i], wl) for i in range(steps)]
     F.fskmc_sync(ctx)
     el = time.perf_counter() - t0
+    P = wl["b"] ** 2 // 64
     if persist > 0:
         launches = sum(-(-o["window"] // persist) for o in obs)
-        kname = (f"k_sweep_{'resident' if resident else 'persistent'}<P={wl['b'] ** 2 // 64},{wl['kind']}> "
+        kname = (f"k_sweep_{'resident' if resident else 'persistent'}<P={P},{wl['kind']}> "
                  f"({persist} windows per launch)")
+        symbol = f"k_sweep_resident<{P}, {wl['b']}, {wl['b']}, {1 if wpg == 1 else 2}, 4>" if resident else None
     else:
         launches = sum(o["window"] for o in obs)
-        kname = f"k_sweep_single<P={wl['b'] ** 2 // 64},{wl['kind']}>"
+        kname = f"k_sweep_single<P={P},{wl['kind']}>"
+        symbol = f"k_sweep_single<{P}, {wl['b']}, {wl['b']}, {1 if wl['kind'] == 'flip' else 2}, {wpg}>"
     rl = roofline(F, ctx, wl["kind"], wl["b"], obs, launches, kname,
-                  resident_sites=wl["Lx"] * wl["Ly"] if resident else 0)
+                  resident_sites=wl["Lx"] * wl["Ly"] if resident else 0, symbol=symbol)
     F.fskmc_ctx_set_kernel_timing(ctx, 0)
     for s in sims:
         s.close()
@@ -297,7 +319,8 @@ def main():
     wl = workloads.c1(J=args.J, dt=args.dt, split=args.split)
     log(f"workload {wl['name']}")
     resident = args.persistent > 0 and not args.no_resident
-    p = bench_plain(F, ctx, wl, args.steps, args.warmup, args.timing_stride, args.persistent, resident)
+    p = bench_plain(F, ctx, wl, args.steps, args.warmup, args.timing_stride, args.persistent, resident,
+                    args.waves_per_group)
     log(f"plain: {args.steps} steps, {p['events']} events in {p['seconds']:.3f} s, "
         f"kernel avg {p['roofline']['avg_launch_us']:.2f} us")
     result = {
@@ -321,7 +344,7 @@ def main():
     }
     if args.persistent > 0:
         F.fskmc_ctx_set_persistent(ctx, 0)
-        q = bench_plain(F, ctx, wl, min(args.steps, 3), 1, args.timing_stride, 0)
+        q = bench_plain(F, ctx, wl, min(args.steps, 3), 1, args.timing_stride, 0, wpg=args.waves_per_group)
         F.fskmc_ctx_set_persistent(ctx, args.persistent)
         result["per_window"] = {"value": q["events"] / q["seconds"], "ms_per_step": q["seconds"] * 1e3 / min(args.steps, 3),
                                 "roofline": q["roofline"]}
@@ -332,7 +355,7 @@ def main():
             for dt in (0.01, 0.1, 1.0):
                 for split in (0, 1):
                     w2 = workloads.c1(J=J, dt=dt, split=split)
-                    q = bench_plain(F, ctx, w2, 1, 1, 0, args.persistent, resident)
+                    q = bench_plain(F, ctx, w2, 1, 1, 0, args.persistent, resident, args.waves_per_group)
                     sweep.append({"workload": w2["name"], "value": q["events"] / q["seconds"],
                                   "ms_per_step": q["seconds"] * 1e3, "events_per_step": q["events"]})
                     log(f"sweep {w2['name']}: {q['events'] / q['seconds']:.3g} events/s")
