@@ -216,6 +216,14 @@ int fskmc_ctx_set_persistent(fskmc_ctx* ctx, int windows);
  * persistent sweep returns FSKMC_EDEVICE the lattice contents are unspecified. */
 int fskmc_ctx_set_resident(fskmc_ctx* ctx, int on);
 
+/* Failure handling: the longest time (seconds, in (0, 60], default 2) a block
+ * of a persistent sweep waits for a neighbour before the sweep aborts; every
+ * wave then leaves and the next synchronising call returns FSKMC_EDEVICE.
+ * After that the simulation's lattice is unspecified until the next
+ * fskmc_sim_init, fskmc_sim_set_lattice or fskmc_sim_set_state.  Tiny values
+ * force the abort path (tests). */
+int fskmc_ctx_set_wait_limit(fskmc_ctx* ctx, double seconds);
+
 /* Measurement aid.  With stride > 0, every stride-th sweep launch on this
  * context is bracketed by two HIP timing events recorded on the context
  * stream (stride 0 turns it off).  read returns the summed duration of the

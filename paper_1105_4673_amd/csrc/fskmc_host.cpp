@@ -87,6 +87,7 @@ struct fskmc_ctx {
     // persistent multi-window sweeps (0 = one launch per window)
     int persist = 0;
     bool resident = true;        // spin flip: keep blocks in LDS across the windows of a launch
+    unsigned long long wait_ticks = 200000000ull; // longest neighbour wait: 2 s of the 100 MHz wall clock
     int32_t* d_abort = nullptr;  // raised by the persistent kernel on a timed-out wait
     int32_t* h_abort = nullptr;  // pinned copy, refreshed after each persistent launch
 };
@@ -459,7 +460,7 @@ int enqueue_persistent(fskmc_sim* S, uint64_t w0, uint64_t w1)
     a.w0 = (int)w0;
     a.w1 = (int)w1;
     a.n_waves = 0;
-    a.wait_ticks = 200000000ull; // two seconds of the 100 MHz wall clock
+    a.wait_ticks = c->wait_ticks;
     const LaunchTiming tk = timing_begin(c);
     HIP_TRY(launch_sweep_persistent(S->model, S->P, S->shape, c->wpg, a, S->max_per_colour, st, tk));
     timing_end(c, tk);
@@ -503,7 +504,7 @@ int enqueue_resident(fskmc_sim* S, uint64_t w0, uint64_t w1)
     a.w1 = (int)w1;
     a.n_waves = 0;
     a.bpw = 0;
-    a.wait_ticks = 200000000ull; // two seconds of the 100 MHz wall clock
+    a.wait_ticks = c->wait_ticks;
     const LaunchTiming tk = timing_begin(c);
     const hipError_t e = launch_sweep_resident(S->P, S->shape, c->wpg, a, st, tk);
     if (e == hipErrorInvalidConfiguration) {
@@ -640,6 +641,17 @@ int fskmc_ctx_set_persistent(fskmc_ctx* c, int windows)
     if (windows < 0)
         return fail(FSKMC_EINVAL, "windows must be >= 0");
     c->persist = windows;
+    return FSKMC_OK;
+}
+
+int fskmc_ctx_set_wait_limit(fskmc_ctx* c, double seconds)
+{
+    if (!c)
+        return fail(FSKMC_EINVAL, "ctx is NULL");
+    if (!(seconds > 0.0) || !(seconds <= 60.0))
+        return fail(FSKMC_EINVAL, "wait limit must be in (0, 60] seconds");
+    const double ticks = seconds * 1e8;
+    c->wait_ticks = ticks < 1.0 ? 1ull : (unsigned long long)ticks;
     return FSKMC_OK;
 }
 

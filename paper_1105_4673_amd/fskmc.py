@@ -66,7 +66,7 @@ SYMBOLS = [
     "fskmc_sim_block_events", "fskmc_sim_rate_table", "fskmc_sim_get_state", "fskmc_sim_set_state",
     "fskmc_sim_footprint", "fskmc_batch_advance", "fskmc_sync", "fskmc_ctx_set_waves_per_group",
     "fskmc_ctx_set_kernel_timing", "fskmc_ctx_read_kernel_timing", "fskmc_ctx_set_persistent",
-    "fskmc_ctx_set_resident",
+    "fskmc_ctx_set_resident", "fskmc_ctx_set_wait_limit",
 ]
 
 
@@ -84,6 +84,7 @@ def _load():
     L.fskmc_ctx_set_kernel_timing.argtypes = [vp, ctypes.c_int]
     L.fskmc_ctx_set_persistent.argtypes = [vp, ctypes.c_int]
     L.fskmc_ctx_set_resident.argtypes = [vp, ctypes.c_int]
+    L.fskmc_ctx_set_wait_limit.argtypes = [vp, ctypes.c_double]
     L.fskmc_ctx_read_kernel_timing.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_uint64)]
     L.fskmc_sim_create.argtypes = [vp, P(fskmc_lattice), ctypes.c_int, vp, P(fskmc_decomp), P(fskmc_schedule),
                                    fskmc_key, P(vp)]
@@ -144,6 +145,10 @@ def fskmc_ctx_set_persistent(ctx, windows):
 
 def fskmc_ctx_set_resident(ctx, on):
     _check(lib.fskmc_ctx_set_resident(ctx, 1 if on else 0))
+
+
+def fskmc_ctx_set_wait_limit(ctx, seconds):
+    _check(lib.fskmc_ctx_set_wait_limit(ctx, seconds))
 
 
 def fskmc_ctx_set_kernel_timing(ctx, stride):

@@ -256,6 +256,13 @@ def test_edge_invalid_inputs(F, ctx):
     with pytest.raises(E):  # state outside the spin space
         s.set_lattice(np.full(4096, 2, np.uint8))
     s.close()
+    for bad in (0.0, -1.0, 61.0, float("nan")):  # wait limit outside (0, 60] s
+        with pytest.raises(E) as ei:
+            F.fskmc_ctx_set_wait_limit(ctx, bad)
+        assert ei.value.code == F.FSKMC_EINVAL
+    with pytest.raises(E) as ei:  # negative windows per persistent launch
+        F.fskmc_ctx_set_persistent(ctx, -1)
+    assert ei.value.code == F.FSKMC_EINVAL
 
 
 def test_edge_zero_length_schedule(F, ctx):
@@ -453,3 +460,38 @@ def test_full_run_matches_oracle_golden(F, ctx, name, persist):
         F.fskmc_ctx_set_persistent(ctx, 0)
         F.fskmc_ctx_set_resident(ctx, 1)
     assert got == (g["sha256"], g["events"])
+
+
+@pytest.mark.parametrize("resident", [1, 0], ids=["resident", "streaming"])
+def test_persistent_wait_timeout_reports_edevice(F, ctx, resident):
+    """Failure handling forced from the host: with a wait limit of one tick of
+    the 100 MHz clock (far below one neighbour hand-off) a persistent sweep
+    aborts, every wave leaving its own bounded wait; the next synchronising
+    call reports FSKMC_EDEVICE, and afterwards the context and the
+    re-initialised simulation give the one-launch-per-window results."""
+    import hashlib
+
+    def run(persist):
+        F.fskmc_ctx_set_persistent(ctx, persist)
+        s.init(1, 0.5)
+        s.advance(40)
+        return hashlib.sha256(s.lattice().tobytes()).hexdigest(), s.observe()["events"]
+
+    s = F.Sim(ctx, FLIP, 256, 256, (1.0, 1.0, 1.0, 0.0, 1.0), b=16, n_colours=2, dt=0.1, T=100.0, split=0, seed=0,
+              replica=1)
+    F.fskmc_ctx_set_resident(ctx, resident)
+    try:
+        F.fskmc_ctx_set_persistent(ctx, 40)
+        F.fskmc_ctx_set_wait_limit(ctx, 1e-8)
+        s.init(1, 0.5)
+        s.advance(40)
+        with pytest.raises(F.FskmcError) as err:
+            F.fskmc_sync(ctx)
+        assert err.value.code == F.FSKMC_EDEVICE
+        F.fskmc_ctx_set_wait_limit(ctx, 2.0)
+        assert run(40) == run(0)
+    finally:
+        F.fskmc_ctx_set_wait_limit(ctx, 2.0)
+        F.fskmc_ctx_set_persistent(ctx, 0)
+        F.fskmc_ctx_set_resident(ctx, 1)
+        s.close()
