@@ -2,7 +2,7 @@
 plausible mistake (a wrong sign, a dropped guard, a wrong neighbour index, a
 wrong half step, a wrong factor, a missing colour test, a wrong constant, a
 wrong key schedule, a transposed direction, a colour
-drawn at the wrong rate) must fail at least one pin.
+drawn at the wrong rate, an off-by-one quantile) must fail at least one pin.
 
 Each variant is compiled on the CPU into a temporary library and the relevant
 pin tests are run against it in a child process."""
@@ -38,6 +38,8 @@ PLANTS = {
     10: ("random schedule drawing one colour per step instead of per window",
          ["test_oracle_fs.py::test_random_schedule_colours_uniform_and_independent",
           "test_oracle_fs.py::test_fs_random_schedule_matches_averaged_propagator"]),
+    11: ("workload quantile one block late (strict instead of non-strict CDF test)",
+         ["test_oracle_balance.py"]),
 }
 
 
@@ -48,7 +50,7 @@ def test_planted_mistake_is_caught(plant):
     with tempfile.TemporaryDirectory() as d:
         lib = os.path.join(d, f"liboracle_plant{plant}.so")
         oracle.build(out=lib, defines=[f"OR_PLANT={plant}"])
-        env = dict(os.environ, FSKMC_ORACLE_LIB=lib, PYTHONPATH=ROOT)
+        env = dict(os.environ, FSKMC_ORACLE_LIB=lib, FSKMC_ORACLE_PLANT=str(plant), PYTHONPATH=ROOT)
         args = [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider"]
         args += [os.path.join(HERE, t) for t in tests]
         res = subprocess.run(args, cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
