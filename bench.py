@@ -28,7 +28,11 @@ Also in the JSON line:
                 [10, 200]) served with continuous batching: p50/p99
                 time-to-result and aggregate events/s;
   sweep         events/s of the other (J, dt, split) points of the 1024^2
-                workload (fewer steps).
+                workload (fewer steps);
+  balance       workload rebalancing (Sec. 5) on a half-filled 2048^2
+                lattice: one launch per window, resident launches on fixed
+                block ranges and on ranges rebalanced from the previous
+                launch's workload histogram, bit-identity checked.
 """
 import argparse
 import json
@@ -243,6 +247,47 @@ def bench_batched(F, ctx, n_jobs, stride, chunk=50):
             "waves_per_group": best, "autotune_s_per_window": timings, "roofline": rl}
 
 
+def bench_balance(F, ctx, windows, chunk):
+    """Workload rebalancing (Sec. 5) on the half-filled 2048^2 lattice: the
+    first `windows` windows with one launch per window, with resident launches
+    of `chunk` windows on fixed block ranges, and on ranges rebalanced from the
+    previous launch's workload; final lattices compared."""
+    import hashlib
+    import numpy as np
+    from paper_1105_4673_amd import workloads
+    wl = workloads.half_filled()
+    N = wl["Lx"] * wl["Ly"]
+    lat0 = np.zeros(N, np.uint8)
+    lat0[N // 2:] = 1
+    out = {"workload": wl["name"], "windows": windows, "windows_per_launch": chunk}
+    digests = []
+    for label, persist, rebalance in (("per_window", 0, 0), ("resident_fixed", chunk, 0),
+                                      ("resident_rebalanced", chunk, 1)):
+        F.fskmc_ctx_set_persistent(ctx, persist)
+        F.fskmc_ctx_set_rebalance(ctx, rebalance)
+        best = None
+        for rep in range(2):  # the first pass also warms the kernels up
+            s = make_sim(F, ctx, wl, replica=3)
+            s.set_lattice(lat0)
+            F.fskmc_sync(ctx)
+            t0 = time.perf_counter()
+            s.advance(windows)
+            F.fskmc_sync(ctx)
+            el = time.perf_counter() - t0
+            ev = s.observe()["events"]
+            dig = hashlib.sha256(s.lattice().tobytes()).hexdigest()
+            s.close()
+            best = el if best is None else min(best, el)
+        out[label] = {"value": ev / best, "seconds": best, "events": ev}
+        digests.append(dig)
+        log(f"balance {label}: {ev / best:.3g} events/s")
+    F.fskmc_ctx_set_rebalance(ctx, 0)
+    F.fskmc_ctx_set_persistent(ctx, 0)
+    out["bit_identical"] = len(set(digests)) == 1
+    out["speedup_rebalanced_vs_fixed"] = out["resident_rebalanced"]["value"] / out["resident_fixed"]["value"]
+    return out
+
+
 def bench_served(F, ctx, rates, n_jobs, windows_per_step, budget_gib):
     """Poisson request streams of mixed Ising / reaction jobs served with
     continuous batching; time-to-result percentiles and aggregate events/s."""
@@ -289,6 +334,9 @@ def main():
     ap.add_argument("--served-jobs", type=int, default=64, help="requests per arrival rate; 0 skips serving")
     ap.add_argument("--served-rates", default="50,200,1000")
     ap.add_argument("--served-windows-per-step", type=int, default=4)
+    ap.add_argument("--balance-windows", type=int, default=200,
+                    help="windows of the half-filled 2048^2 rebalancing comparison; 0 skips it")
+    ap.add_argument("--balance-chunk", type=int, default=20)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -360,6 +408,8 @@ def main():
                                   "ms_per_step": q["seconds"] * 1e3, "events_per_step": q["events"]})
                     log(f"sweep {w2['name']}: {q['events'] / q['seconds']:.3g} events/s")
         result["sweep"] = sweep
+    if args.balance_windows:
+        result["balance"] = bench_balance(F, ctx, args.balance_windows, args.balance_chunk)
     F.fskmc_ctx_set_persistent(ctx, 0)  # batched and served runs use one packed launch per window
     if args.batched_jobs:
         F.fskmc_ctx_set_waves_per_group(ctx, args.waves_per_group)

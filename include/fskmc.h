@@ -216,6 +216,39 @@ int fskmc_ctx_set_persistent(fskmc_ctx* ctx, int windows);
  * persistent sweep returns FSKMC_EDEVICE the lattice contents are unspecified. */
 int fskmc_ctx_set_resident(fskmc_ctx* ctx, int on);
 
+/* Knob that never changes results (default off): resident persistent sweeps
+ * give each wave a contiguous range of blocks (block order m = bj*NBX + bi)
+ * by the mass-transport map (fskmc_workload_partition, capacity = the blocks
+ * a wave holds: 8 for 8x8 and 16x16 blocks, 4 for 32x32) of the block costs
+ * since the simulation's previous rebalanced launch, instead of fixed pairs.
+ * A block's cost is its jumps in those windows plus 3 per window of its
+ * colour there (a block-window's fixed work is about that of three jumps);
+ * the first launch splits evenly.  The map is computed on the device between
+ * launches, over max(ceil(n_blocks/2), ceil(n_blocks/capacity)) waves (at most
+ * the resident waves). */
+int fskmc_ctx_set_rebalance(fskmc_ctx* ctx, int on);
+
+/* Workload histogram (Sec. 5, eq. wload): out[m] = accepted events of block m
+ * (block order m = bj*NBX + bi) since the last fskmc_sim_init, set_lattice or
+ * set_state.  n_blocks must equal the simulation's block count.  Synchronises
+ * the context's stream. */
+int fskmc_sim_workload(fskmc_sim* sim, uint64_t* out, size_t n_blocks);
+
+/* Mass-transport map of a workload histogram W[0..M) onto P processors
+ * (Sec. 5): bounds[0..P] (P+1 entries, caller-owned) with processor l owning
+ * blocks [bounds[l], bounds[l+1]); bounds[l] is the first k with
+ * P*(W[0] + ... + W[k-1]) >= l * total (a histogram without mass counts every
+ * block once).  With cap > 0, when some range would hold more than cap
+ * blocks the even split bounds[l] = floor(l*M/P) is returned instead.  Host
+ * only.  FSKMC_EINVAL for M < 0, P < 1, cap < 0, NULL arrays or M > P*cap. */
+int fskmc_workload_partition(const uint64_t* W, int M, int P, int cap, int32_t* bounds);
+
+/* The block ranges of the simulation's last rebalanced resident launch:
+ * *n_out = number of boundaries (resident waves + 1; 0 if none yet), copied
+ * to out when n >= *n_out; n = 0 only queries the size, 0 < n < *n_out is
+ * FSKMC_EINVAL. */
+int fskmc_sim_last_partition(const fskmc_sim* sim, int32_t* out, size_t n, size_t* n_out);
+
 /* Failure handling: the longest time (seconds, in (0, 60], default 2) a block
  * of a persistent sweep waits for a neighbour before the sweep aborts; every
  * wave then leaves and the next synchronising call returns FSKMC_EDEVICE.

@@ -12,9 +12,12 @@ P * C(k) >= l * total, and processor l owns blocks [boundary l-1, boundary l).
 A histogram with no mass is treated as uniform.
 
 A processor of the GPU library (a resident wave) holds at most `cap` blocks,
-and a boundary must leave the remaining processors able to cover the rest;
-when `cap` is given each boundary is clamped into that feasible interval.
-The clamp is the library's addition to the paper's map.
+and a boundary must leave the remaining processors able to cover the rest:
+when `cap` is given, boundary l is clamped into
+[max(b_{l-1}, M - (P-l) cap), min(b_{l-1} + cap, M)], taken in order.  The
+capacity clamp, and the block cost the library feeds in (jumps plus a fixed
+cost per block and window, `block_costs`), are the library's additions to
+the paper's map.
 """
 import os
 
@@ -41,16 +44,20 @@ def cdf_partition(W, P, cap=None):
             cum += weights[k]
             k += 1
         b = k
-        prev = bounds[-1]
-        if cap is None:
-            b = max(b, prev)
-        else:
+        if cap is not None:
+            prev = bounds[-1]
             lo = max(prev, M - (P - l) * cap)
             hi = min(prev + cap, M)
             b = min(max(b, lo), hi)
         bounds.append(b)
     bounds.append(M)
     return bounds
+
+
+def block_costs(W, colours, active, base):
+    """The library's block cost for rebalancing: jumps of block m plus `base`
+    for every window its colour took part in (active[c] windows of colour c)."""
+    return [int(w) + base * int(active[int(c)]) for w, c in zip(W, colours)]
 
 
 def part_masses(W, bounds):

@@ -87,6 +87,7 @@ struct fskmc_ctx {
     // persistent multi-window sweeps (0 = one launch per window)
     int persist = 0;
     bool resident = true;        // spin flip: keep blocks in LDS across the windows of a launch
+    bool rebalance = false;      // resident launches: block ranges by the workload of the previous launch
     unsigned long long wait_ticks = 200000000ull; // longest neighbour wait: 2 s of the 100 MHz wall clock
     int32_t* d_abort = nullptr;  // raised by the persistent kernel on a timed-out wait
     int32_t* h_abort = nullptr;  // pinned copy, refreshed after each persistent launch
@@ -130,6 +131,15 @@ struct fskmc_sim {
     std::vector<int32_t> prev_part;  // [n_colours][n_windows+1]
     int32_t* d_prev = nullptr;
     unsigned long long* d_edge = nullptr;
+    // workload rebalancing: per-block events at the previous resident launch
+    // and its windows, prefix-sum scratch, the block ranges of the last
+    // rebalanced launch (n_owner boundaries)
+    bool have_prev = false;
+    uint64_t rb_w0 = 0;  // first window of the previous rebalanced launch
+    unsigned long long* d_ev_prev = nullptr;
+    unsigned long long* d_scan = nullptr;
+    int32_t* d_owner = nullptr;
+    size_t n_owner = 0, cap_owner = 0;
 };
 
 namespace {
@@ -349,6 +359,9 @@ void free_sim_device(fskmc_sim* S)
     (void)hipFree(S->d_epoch);
     (void)hipFree(S->d_prev);
     (void)hipFree(S->d_edge);
+    (void)hipFree(S->d_owner);
+    (void)hipFree(S->d_ev_prev);
+    (void)hipFree(S->d_scan);
     S->d_lat = nullptr;
 }
 
@@ -403,6 +416,7 @@ int reset_counters(fskmc_sim* S)
 {
     hipStream_t st = S->ctx->stream;
     S->block_windows = 0;
+    S->have_prev = false;
     HIP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(S->d_cnt), 2 * (int64_t)S->nb, 0ull, st));
     return FSKMC_OK;
 }
@@ -472,6 +486,84 @@ int enqueue_persistent(fskmc_sim* S, uint64_t w0, uint64_t w1)
     return FSKMC_OK;
 }
 
+// Mass-transport map of a workload histogram onto P processors (Sec. 5):
+// boundary l is the first k with P * (W[0] + ... + W[k-1]) >= l * total (a
+// histogram without mass counts every block once), clamped in order into
+// [max(b_{l-1}, M - (P-l) cap), min(b_{l-1} + cap, M)] when a capacity is
+// given.
+void cdf_ranges(const uint64_t* W, int M, int P, int cap, int32_t* bounds)
+{
+    unsigned __int128 total = 0;
+    for (int m = 0; m < M; ++m)
+        total += W[m];
+    const bool flat = total == 0;
+    if (flat)
+        total = (unsigned)M;
+    bounds[0] = 0;
+    unsigned __int128 cum = 0;
+    int k = 0;
+    for (int l = 1; l < P; ++l) {
+        const unsigned __int128 target = (unsigned __int128)l * total;
+        while (k < M && cum * (unsigned)P < target) {
+            cum += flat ? 1u : W[k];
+            ++k;
+        }
+        int64_t b = k;
+        if (cap > 0) {
+            const int64_t prev = bounds[l - 1];
+            const int64_t lo = std::max<int64_t>(prev, (int64_t)M - (int64_t)(P - l) * cap);
+            const int64_t hi = std::min<int64_t>(prev + cap, M);
+            b = std::min(std::max(b, lo), hi);
+        }
+        bounds[l] = (int32_t)b;
+    }
+    bounds[P] = M;
+}
+
+// Fixed cost of one block-window in units of one jump's cost, the block cost
+// of the rebalancing map (measured: staging, tree build and edge exchange
+// take about as long as three events).
+constexpr unsigned long long kWindowCost = 3;
+
+// Block ranges of the next resident launch, computed on the device from the
+// workload since the previous rebalanced launch (an even split the first
+// time; otherwise the jumps of windows [previous start, w0) plus kWindowCost
+// per window of the block's colour in that range) over as many waves as an
+// even split would use (two blocks per wave, more if the lattice needs it),
+// each range at most the wave's capacity; the remaining resident waves get
+// empty ranges.  Returns 1 when the blocks do not fit the resident waves.
+int rebalance_ranges(fskmc_sim* S, uint64_t w0)
+{
+    fskmc_ctx* c = S->ctx;
+    const int waves = resident_waves(S->P, S->shape, c->wpg);
+    const int cap = resident_capacity(S->P);
+    if (waves <= 0 || (int64_t)S->nb > (int64_t)waves * cap)
+        return 1;
+    if (!S->d_ev_prev) {
+        if (int rc = dev_alloc(&S->d_ev_prev, S->nb))
+            return rc;
+        if (int rc = dev_alloc(&S->d_scan, S->nb))
+            return rc;
+    }
+    if (S->cap_owner < (size_t)waves + 1) {
+        (void)hipFree(S->d_owner);
+        S->d_owner = nullptr;
+        S->cap_owner = 0;
+        if (int rc = dev_alloc(&S->d_owner, (size_t)waves + 1))
+            return rc;
+        S->cap_owner = (size_t)waves + 1;
+    }
+    const int use = std::min(waves, std::max((S->nb + 1) / 2, (S->nb + cap - 1) / cap));
+    // the jumps since the previous rebalanced launch cover windows [rb_w0, w0)
+    HIP_TRY(launch_rebalance(S->d_cnt, S->d_ev_prev, S->d_bcol, S->d_wcol, (int)S->rb_w0, (int)w0,
+                             S->have_prev ? 0 : 1, kWindowCost, S->d_scan, S->d_owner, S->nb, use, waves, cap,
+                             c->stream));
+    S->have_prev = true;
+    S->rb_w0 = w0;
+    S->n_owner = (size_t)waves + 1;
+    return FSKMC_OK;
+}
+
 // Windows [w0, w1) of a spin-flip simulation in one resident launch: edge
 // tags set to a value no window expects, the abort flag cleared, one
 // cooperative launch.  Returns 1 (nothing enqueued but the fill) when the
@@ -504,7 +596,17 @@ int enqueue_resident(fskmc_sim* S, uint64_t w0, uint64_t w1)
     a.w1 = (int)w1;
     a.n_waves = 0;
     a.bpw = 0;
+    a.owner = nullptr;
     a.wait_ticks = c->wait_ticks;
+    if (c->rebalance) {
+        int rc = rebalance_ranges(S, w0);
+        if (rc == 1)
+            return 1;
+        if (rc)
+            return rc;
+        a.owner = S->d_owner;
+        a.n_waves = (int)S->n_owner - 1;
+    }
     const LaunchTiming tk = timing_begin(c);
     const hipError_t e = launch_sweep_resident(S->P, S->shape, c->wpg, a, st, tk);
     if (e == hipErrorInvalidConfiguration) {
@@ -653,6 +755,53 @@ int fskmc_ctx_set_wait_limit(fskmc_ctx* c, double seconds)
     const double ticks = seconds * 1e8;
     c->wait_ticks = ticks < 1.0 ? 1ull : (unsigned long long)ticks;
     return FSKMC_OK;
+}
+
+int fskmc_ctx_set_rebalance(fskmc_ctx* c, int on)
+{
+    if (!c)
+        return fail(FSKMC_EINVAL, "ctx is NULL");
+    c->rebalance = on != 0;
+    return FSKMC_OK;
+}
+
+int fskmc_workload_partition(const uint64_t* W, int M, int P, int cap, int32_t* bounds)
+{
+    if (M < 0 || P < 1 || cap < 0 || (M > 0 && !W) || !bounds)
+        return fail(FSKMC_EINVAL, "need M >= 0, P >= 1, cap >= 0 and non-NULL arrays");
+    if (cap > 0 && (int64_t)M > (int64_t)P * cap)
+        return fail(FSKMC_EINVAL, "%d blocks do not fit %d processors of capacity %d", M, P, cap);
+    cdf_ranges(W, M, P, cap, bounds);
+    return FSKMC_OK;
+}
+
+int fskmc_sim_workload(fskmc_sim* S, uint64_t* out, size_t n_blocks)
+{
+    if (!S || !out)
+        return fail(FSKMC_EINVAL, "NULL argument");
+    if (n_blocks != (size_t)S->nb)
+        return fail(FSKMC_EINVAL, "sim has %d blocks, got %zu", S->nb, n_blocks);
+    std::vector<BlockCount> rec(n_blocks);
+    HIP_TRY(hipMemcpyAsync(rec.data(), S->d_cnt, n_blocks * sizeof(BlockCount), hipMemcpyDeviceToHost,
+                           S->ctx->stream));
+    HIP_TRY(hipStreamSynchronize(S->ctx->stream));
+    for (size_t i = 0; i < n_blocks; ++i)
+        out[i] = rec[i].events;
+    return check_abort(S->ctx);
+}
+
+int fskmc_sim_last_partition(const fskmc_sim* S, int32_t* out, size_t n, size_t* n_out)
+{
+    if (!S || !n_out || (n > 0 && !out))
+        return fail(FSKMC_EINVAL, "NULL argument");
+    *n_out = S->n_owner;
+    if (S->n_owner == 0 || n == 0) // n == 0: size query
+        return FSKMC_OK;
+    if (n < S->n_owner)
+        return fail(FSKMC_EINVAL, "need room for %zu boundaries", S->n_owner);
+    HIP_TRY(hipMemcpyAsync(out, S->d_owner, S->n_owner * 4, hipMemcpyDeviceToHost, S->ctx->stream));
+    HIP_TRY(hipStreamSynchronize(S->ctx->stream));
+    return check_abort(S->ctx);
 }
 
 int fskmc_ctx_set_resident(fskmc_ctx* c, int on)

@@ -84,6 +84,7 @@ struct ResidentArgs {
     const double* win_dur;      // per window
     const int32_t* prev_part;   // [n_colours][n_windows+1]: last window < w of colour c, -1 if none
     unsigned long long* edge;   // [n_blocks][4]: tag | bits << 32 of the first/last row, first/last column
+    const int32_t* owner;       // [n_waves+1] block range of each wave, or null: wave g owns g*bpw .. +bpw-1
     int32_t* abort_flag;        // raised by a wave whose wait timed out
     int Lx, Ly, NBX, NBY, nb;
     uint32_t k0, k1;
@@ -111,6 +112,17 @@ hipError_t launch_sweep_persistent(int model, int P, int shape, int wpg, const P
 // hipErrorInvalidConfiguration when the blocks do not fit the resident waves
 // (the caller then uses the streaming persistent sweep).
 hipError_t launch_sweep_resident(int P, int shape, int wpg, const ResidentArgs& a, hipStream_t s, LaunchTiming tm);
+// Waves the resident sweep can keep resident and blocks one wave can hold
+// (with an owner array, a.n_waves must be resident_waves(...) and every range
+// at most resident_capacity(P) blocks).
+int resident_waves(int P, int shape, int wpg);
+int resident_capacity(int P);
+// Block ranges of the next resident launch from the previous launch's
+// workload (one workgroup; see k_rebalance).
+hipError_t launch_rebalance(const BlockCount* cnt, unsigned long long* ev_prev, const int8_t* bcol,
+                            const int8_t* win_colour, int pw0, int pw1, int first, unsigned long long base,
+                            unsigned long long* scan, int32_t* owner, int nb, int use, int n_waves, int cap,
+                            hipStream_t s);
 hipError_t launch_epoch_init(int32_t* epoch, const int8_t* bcol, const int32_t* next_part, int nb, int n_windows,
                              int w0, hipStream_t s);
 hipError_t launch_init(uint8_t* lat, int64_t n, int kind, double p, uint32_t k0, uint32_t k1,

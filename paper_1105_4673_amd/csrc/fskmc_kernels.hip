@@ -974,7 +974,8 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
     double* tab = reinterpret_cast<double*>(wl + BPW * C::TILE);
     uint32_t* ledge = reinterpret_cast<uint32_t*>(wl + BPW * C::TILE + C::NTAB * 8 + C::XFER); // [BPW][4]
     const int gw = (int)xcd_order(blockIdx.x, gridDim.x) * WPG + wid;
-    const int m0 = gw * a.bpw;
+    const int m0 = a.owner ? a.owner[gw] : gw * a.bpw;
+    const int want_own = a.owner ? a.owner[gw + 1] - m0 : a.bpw;
     const int r = lane / C::LPR, c0 = (lane % C::LPR) * P;
     const int tb = (r + 1) * C::S + P + c0;
     const size_t sLx = (size_t)a.Lx;
@@ -982,14 +983,15 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
     for (int i = lane; i < C::NTAB; i += 64)
         tab[i] = a.table[i];
     int nown = 0;
-    uint32_t cols = 0; // colour of owned block i in byte i
-    for (int i = 0; i < a.bpw; ++i) {
+    static_assert(BPW <= 8, "one colour byte per owned block");
+    uint64_t cols = 0; // colour of owned block i in byte i
+    for (int i = 0; i < want_own && i < BPW; ++i) {
         const int m = m0 + i;
         if (m >= a.nb)
             break;
         const int x0 = (m % a.NBX) * BX, y0 = (m / a.NBX) * BY;
         store_seg<P>(wl + i * C::TILE + tb, load_seg<P>(a.lat + (size_t)(y0 + r) * sLx + x0 + c0));
-        cols |= (uint32_t)(uint8_t)a.bcol[m] << (8 * i);
+        cols |= (uint64_t)(uint8_t)a.bcol[m] << (8 * i);
         nown = i + 1;
     }
     wave_sync();
@@ -1100,6 +1102,116 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
         const int x0 = (m % a.NBX) * BX, y0 = (m / a.NBX) * BY;
         store_seg<P>(a.lat + (size_t)(y0 + r) * sLx + x0 + c0, load_seg<P>(wl + i * C::TILE + tb));
     }
+}
+
+// ---------------------------------------------------------------------------
+// Block ranges of the next resident launch from the workload of the previous
+// one (Sec. 5: the cumulative distribution of the workload histogram mapped
+// onto equal masses over the processors), in one workgroup between launches.
+// cost(m) = jumps of block m since the previous launch + base x (windows of
+// its colour in that launch), or 1 for every block on the first launch; the
+// costs' prefix sums C (C(0) = 0) give the quantile q_l = the first k with
+// use * C(k) >= l * total (C(k) = k when the costs have no mass), clamped in
+// order into [max(b_{l-1}, nb - (use-l) cap), min(b_{l-1} + cap, nb)].  With
+// x_l = max(q_l, nb - (use-l) cap), which is non-decreasing and at most nb,
+// that clamp is b_l = min(x_l, b_{l-1} + cap) = min over j <= l of
+// x_j + (l-j) cap (x_0 = 0): a prefix minimum.  Waves use .. n_waves-1 get
+// empty ranges.  ev_prev keeps the cumulative jump counts for the next call;
+// scan holds nb prefix sums.
+__global__ __launch_bounds__(1024) void k_rebalance(const BlockCount* cnt, unsigned long long* ev_prev,
+                                                    const int8_t* bcol, const int8_t* win_colour, int pw0, int pw1,
+                                                    int first, unsigned long long base, unsigned long long* scan,
+                                                    int32_t* owner, int nb, int use, int n_waves, int cap)
+{
+    __shared__ unsigned long long part[1024];
+    __shared__ long long pmin[1024];
+    __shared__ unsigned int act[256];
+    const int t = threadIdx.x;
+    if (t < 256)
+        act[t] = 0;
+    __syncthreads();
+    if (!first)
+        for (int w = pw0 + t; w < pw1; w += 1024)
+            atomicAdd(&act[(uint8_t)win_colour[w]], 1u);
+    __syncthreads();
+    const int chunk = (nb + 1023) / 1024;
+    const int b0 = min(t * chunk, nb), b1 = min(b0 + chunk, nb);
+    unsigned long long sum = 0;
+    for (int m = b0; m < b1; ++m) {
+        const unsigned long long ev = cnt[m].events;
+        sum += first ? 1ull : ev - ev_prev[m] + base * act[(uint8_t)bcol[m]];
+        ev_prev[m] = ev;
+        scan[m] = sum; // prefix within the thread's run of blocks
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) { // inclusive scan of the run sums
+        const unsigned long long v = t >= off ? part[t - off] : 0ull;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    const unsigned long long before = t > 0 ? part[t - 1] : 0ull, total = part[1023];
+    for (int m = b0; m < b1; ++m)
+        scan[m] += before; // C(m + 1)
+    __syncthreads();
+    for (int l = 1 + t; l < use; l += 1024) {
+        int k;
+        if (total == 0) {
+            k = (int)(((long long)l * nb + use - 1) / use);
+        } else {
+            const unsigned __int128 target = (unsigned __int128)l * total;
+            int lo = 0, hi = nb;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                const unsigned long long C = mid == 0 ? 0ull : scan[mid - 1];
+                if ((unsigned __int128)C * (unsigned)use >= target)
+                    hi = mid;
+                else
+                    lo = mid + 1;
+            }
+            k = lo;
+        }
+        owner[l] = k;
+    }
+    if (t == 0)
+        owner[0] = 0;
+    for (int l = use + t; l <= n_waves; l += 1024)
+        owner[l] = nb;
+    __syncthreads();
+    // clamp: b_l = l cap + min over j <= l of (x_j - j cap), over runs of l
+    const int lrun = (use + 1 + 1023) / 1024;
+    const int l0 = min(t * lrun, use + 1), l1 = min(l0 + lrun, use + 1);
+    constexpr long long kNone = 0x7fffffffffffffffll;
+    long long run_min = kNone;
+    for (int l = l0; l < l1; ++l) {
+        const long long x = l == 0 ? 0ll : max((long long)owner[l], (long long)nb - (long long)(use - l) * cap);
+        run_min = min(run_min, x - (long long)l * cap);
+    }
+    pmin[t] = run_min;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) { // inclusive prefix minimum of the run minima
+        const long long v = t >= off ? pmin[t - off] : kNone;
+        __syncthreads();
+        pmin[t] = min(pmin[t], v);
+        __syncthreads();
+    }
+    long long m = t > 0 ? pmin[t - 1] : kNone;
+    for (int l = l0; l < l1; ++l) { // each thread reads and rewrites only its own run
+        const long long x = l == 0 ? 0ll : max((long long)owner[l], (long long)nb - (long long)(use - l) * cap);
+        m = min(m, x - (long long)l * cap);
+        owner[l] = (int32_t)(m + (long long)l * cap);
+    }
+}
+
+hipError_t launch_rebalance(const BlockCount* cnt, unsigned long long* ev_prev, const int8_t* bcol,
+                            const int8_t* win_colour, int pw0, int pw1, int first, unsigned long long base,
+                            unsigned long long* scan, int32_t* owner, int nb, int use, int n_waves, int cap,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rebalance, dim3(1), dim3(1024), 0, s, cnt, ev_prev, bcol, win_colour, pw0, pw1, first, base,
+                       scan, owner, nb, use, n_waves, cap);
+    return hipGetLastError();
 }
 
 // epoch[m] = the first window >= w0 that block m takes part in.
@@ -1323,41 +1435,57 @@ static hipError_t persist_launch(PersistArgs a, int max_blocks_per_colour, hipSt
     return e;
 }
 
-// Cooperative launch of the resident sweep: one wave per block while the
-// blocks fit the resident waves, up to RES_BPW blocks per wave beyond that.
-constexpr int RES_BPW = 4;
+// Cooperative launch of the resident sweep: an adjacent block pair per wave,
+// more blocks per wave (up to res_bpw) when the lattice has more blocks than
+// twice the resident waves, or the caller's ranges (owner array, one range
+// per resident wave).
+constexpr int res_bpw(int P) { return P == 16 ? 4 : 8; }
+
+template <int P, int BX, int BY, int WPG>
+static int resident_groups_of()
+{
+    auto kern = k_sweep_resident<P, BX, BY, WPG, res_bpw(P)>;
+    static int resident_groups = 0;
+    if (resident_groups == 0) {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * WPG, 0) != hipSuccess ||
+            hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0; // no resident launch possible: the caller streams
+        resident_groups = per_cu * cus;
+    }
+    return resident_groups;
+}
 
 template <int P, int BX, int BY, int WPG>
 static hipError_t resident_launch(ResidentArgs a, hipStream_t s, LaunchTiming tm)
 {
-    auto kern = k_sweep_resident<P, BX, BY, WPG, RES_BPW>;
-    static int resident_groups = 0;
-    if (resident_groups == 0) {
-        int per_cu = 0, dev = 0, cus = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * WPG, 0);
-        if (e != hipSuccess)
-            return e;
-        if ((e = hipGetDevice(&dev)) != hipSuccess ||
-            (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
-            return e;
-        resident_groups = per_cu * cus;
-        if (resident_groups <= 0)
-            return hipErrorInvalidConfiguration;
-    }
+    auto kern = k_sweep_resident<P, BX, BY, WPG, res_bpw(P)>;
+    const int resident_groups = resident_groups_of<P, BX, BY, WPG>();
+    if (resident_groups <= 0)
+        return hipErrorInvalidConfiguration;
     if (a.nb <= 0)
         return hipErrorInvalidValue;
-    // two blocks per wave (an adjacent pair of the two colours), more when the
-    // lattice has more blocks than twice the resident waves
-    const int cap = resident_groups * WPG;
-    int bpw = a.nb >= 2 ? 2 : 1;
-    if (bpw * cap < a.nb)
-        bpw = (a.nb + cap - 1) / cap;
-    if (bpw > RES_BPW)
-        return hipErrorInvalidConfiguration;
-    a.bpw = bpw;
-    const int waves = (a.nb + bpw - 1) / bpw;
-    const int groups = (waves + WPG - 1) / WPG;
-    a.n_waves = groups * WPG;
+    int groups = 0;
+    if (a.owner) {
+        if (a.n_waves != resident_groups * WPG)
+            return hipErrorInvalidValue;
+        groups = resident_groups;
+        a.bpw = 0;
+    } else {
+        // two blocks per wave (an adjacent pair of the two colours), more when
+        // the lattice has more blocks than twice the resident waves
+        const int cap = resident_groups * WPG;
+        int bpw = a.nb >= 2 ? 2 : 1;
+        if (bpw * cap < a.nb)
+            bpw = (a.nb + cap - 1) / cap;
+        if (bpw > res_bpw(P))
+            return hipErrorInvalidConfiguration;
+        a.bpw = bpw;
+        const int waves = (a.nb + bpw - 1) / bpw;
+        groups = (waves + WPG - 1) / WPG;
+        a.n_waves = groups * WPG;
+    }
     void* args[] = {&a};
     if (tm.start)
         (void)hipEventRecord(tm.start, s);
@@ -1393,6 +1521,26 @@ hipError_t launch_sweep_resident(int P, int shape, int wpg, const ResidentArgs& 
 {
     return wpg == 1 ? resident_dispatch<1>(P, shape, a, s, tm) : resident_dispatch<2>(P, shape, a, s, tm);
 }
+
+template <int WPG>
+static int resident_waves_of(int P, int shape)
+{
+    int g = 0;
+    if (shape == SHAPE_SQ)
+        g = P == 1 ? resident_groups_of<1, 8, 8, WPG>() : P == 4 ? resident_groups_of<4, 16, 16, WPG>()
+                                                                 : resident_groups_of<16, 32, 32, WPG>();
+    else
+        g = P == 1 ? resident_groups_of<1, 64, 1, WPG>() : P == 4 ? resident_groups_of<4, 256, 1, WPG>()
+                                                                  : resident_groups_of<16, 1024, 1, WPG>();
+    return g * WPG;
+}
+
+int resident_waves(int P, int shape, int wpg)
+{
+    return wpg == 1 ? resident_waves_of<1>(P, shape) : resident_waves_of<2>(P, shape);
+}
+
+int resident_capacity(int P) { return res_bpw(P); }
 
 template <int MODEL, int WPG>
 static hipError_t persist_dispatch(int P, int shape, const PersistArgs& a, int maxpc, hipStream_t s, LaunchTiming tm)

@@ -66,7 +66,8 @@ SYMBOLS = [
     "fskmc_sim_block_events", "fskmc_sim_rate_table", "fskmc_sim_get_state", "fskmc_sim_set_state",
     "fskmc_sim_footprint", "fskmc_batch_advance", "fskmc_sync", "fskmc_ctx_set_waves_per_group",
     "fskmc_ctx_set_kernel_timing", "fskmc_ctx_read_kernel_timing", "fskmc_ctx_set_persistent",
-    "fskmc_ctx_set_resident", "fskmc_ctx_set_wait_limit",
+    "fskmc_ctx_set_resident", "fskmc_ctx_set_wait_limit", "fskmc_ctx_set_rebalance", "fskmc_sim_workload",
+    "fskmc_workload_partition", "fskmc_sim_last_partition",
 ]
 
 
@@ -85,6 +86,11 @@ def _load():
     L.fskmc_ctx_set_persistent.argtypes = [vp, ctypes.c_int]
     L.fskmc_ctx_set_resident.argtypes = [vp, ctypes.c_int]
     L.fskmc_ctx_set_wait_limit.argtypes = [vp, ctypes.c_double]
+    L.fskmc_ctx_set_rebalance.argtypes = [vp, ctypes.c_int]
+    L.fskmc_sim_workload.argtypes = [vp, P(ctypes.c_uint64), ctypes.c_size_t]
+    L.fskmc_workload_partition.argtypes = [P(ctypes.c_uint64), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           P(ctypes.c_int32)]
+    L.fskmc_sim_last_partition.argtypes = [vp, P(ctypes.c_int32), ctypes.c_size_t, P(ctypes.c_size_t)]
     L.fskmc_ctx_read_kernel_timing.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_uint64)]
     L.fskmc_sim_create.argtypes = [vp, P(fskmc_lattice), ctypes.c_int, vp, P(fskmc_decomp), P(fskmc_schedule),
                                    fskmc_key, P(vp)]
@@ -149,6 +155,35 @@ def fskmc_ctx_set_resident(ctx, on):
 
 def fskmc_ctx_set_wait_limit(ctx, seconds):
     _check(lib.fskmc_ctx_set_wait_limit(ctx, seconds))
+
+
+def fskmc_ctx_set_rebalance(ctx, on):
+    _check(lib.fskmc_ctx_set_rebalance(ctx, 1 if on else 0))
+
+
+def fskmc_sim_workload(sim, n_blocks):
+    a = np.empty(n_blocks, np.uint64)
+    _check(lib.fskmc_sim_workload(sim, a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), n_blocks))
+    return a
+
+
+def fskmc_workload_partition(W, P, cap=0):
+    W = np.ascontiguousarray(W, dtype=np.uint64)
+    out = np.empty(P + 1, np.int32)
+    _check(lib.fskmc_workload_partition(W.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), len(W), P, cap,
+                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return out
+
+
+def fskmc_sim_last_partition(sim):
+    n = ctypes.c_size_t()
+    _check(lib.fskmc_sim_last_partition(sim, None, 0, ctypes.byref(n)))
+    if n.value == 0:
+        return None
+    out = np.empty(n.value, np.int32)
+    _check(lib.fskmc_sim_last_partition(sim, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n.value,
+                                        ctypes.byref(n)))
+    return out
 
 
 def fskmc_ctx_set_kernel_timing(ctx, stride):
@@ -320,6 +355,12 @@ class Sim:
 
     def observe(self):
         return fskmc_sim_observe(self.handle)
+
+    def workload(self):
+        return fskmc_sim_workload(self.handle, self.nb)
+
+    def last_partition(self):
+        return fskmc_sim_last_partition(self.handle)
 
     def block_events(self):
         return fskmc_sim_block_events(self.handle, self.nb)

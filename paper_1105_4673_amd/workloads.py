@@ -69,3 +69,12 @@ def c4_requests(rate, n=256, seed=None, max_edge=2048):
         job.update(name=f"req{i}", arrival=float(arrivals[i]), seed=0, replica=i)
         reqs.append(job)
     return reqs
+
+
+def half_filled(L=2048, J=1.0, dt=0.1, T=100.0):
+    """L^2 spin flip, 16x16 blocks, Lie dt, the lower half of the rows empty
+    and the upper half full: the empty half adsorbs at rate k_a while the full
+    half hardly desorbs (k_d exp(-4 beta J)), a strongly unbalanced workload
+    like the coverage gradient of the paper's rebalancing example."""
+    return dict(name=f"ising{L}_b16_J{J:g}_lie_dt{dt:g}_half_filled", kind="flip", Lx=L, Ly=L,
+                params=(1.0, 1.0, J, 0.0, 1.0), b=16, n_colours=2, dt=dt, T=T, split=0, init="half")

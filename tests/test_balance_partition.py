@@ -1,0 +1,47 @@
+"""The library's workload partition (host code behind the C ABI, no GPU
+needed) equals the oracle's mass-transport map (Sec. 5) element by element,
+on random histograms with idle stretches, spikes and capacities, on the
+extreme sizes the resident sweep uses, and rejects invalid inputs."""
+import numpy as np
+import pytest
+
+from oracle import balance
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_1105_4673_amd import fskmc
+    return fskmc
+
+
+def test_partition_matches_oracle_random(F):
+    rng = np.random.default_rng(11)
+    for _ in range(400):
+        P = int(rng.integers(1, 64))
+        cap = int(rng.integers(0, 9))
+        M = int(rng.integers(0, (P * cap if cap else 300) + 1))
+        W = rng.integers(0, 1000, size=M)
+        if M and rng.random() < 0.4:
+            W[: M // 2] = 0  # an idle half
+        if M and rng.random() < 0.3:
+            W[int(rng.integers(0, M))] = 10 ** 12  # a spike
+        got = F.fskmc_workload_partition(W, P, cap)
+        want = balance.cdf_partition(W.tolist(), P, cap if cap else None)
+        assert got.tolist() == want, (M, P, cap)
+
+
+@pytest.mark.parametrize("M,P,cap", [(4096, 2048, 8), (16384, 4096, 8), (16384, 2048, 8), (65536, 8192, 8),
+                                     (1, 1, 0), (0, 3, 0)])
+def test_partition_matches_oracle_large(F, M, P, cap):
+    rng = np.random.default_rng(M + P)
+    W = rng.poisson(3.0, size=M).astype(np.uint64)
+    W[: M // 3] = 0
+    got = F.fskmc_workload_partition(W, P, cap)
+    assert got.tolist() == balance.cdf_partition(W.tolist(), P, cap if cap else None)
+
+
+def test_partition_rejects_invalid(F):
+    with pytest.raises(F.FskmcError):
+        F.fskmc_workload_partition(np.ones(10, np.uint64), 2, 4)  # 10 blocks > 2 x 4
+    with pytest.raises(F.FskmcError):
+        F.fskmc_workload_partition(np.ones(3, np.uint64), 0, 0)

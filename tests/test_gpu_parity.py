@@ -495,3 +495,61 @@ def test_persistent_wait_timeout_reports_edevice(F, ctx, resident):
         F.fskmc_ctx_set_persistent(ctx, 0)
         F.fskmc_ctx_set_resident(ctx, 1)
         s.close()
+
+
+@pytest.mark.parametrize("L,chunk", [(512, 25), (2048, 10)], ids=["512-pairs", "2048-capacity-bound"])
+def test_rebalanced_resident(F, ctx, L, chunk):
+    """Workload rebalancing (Sec. 5) on a half-filled lattice (the empty half
+    adsorbs, the full half is nearly idle): every resident launch takes its
+    block ranges from the oracle's mass-transport map of the block costs of
+    the previous launch (jumps plus 3 per window of the block's colour; an
+    even split the first time), and the run is bit-for-bit the
+    one-launch-per-window run."""
+    import hashlib
+    from oracle import balance
+    N = L * L
+    lat0 = np.zeros(N, np.uint8)
+    lat0[N // 2:] = 1
+    prm = (1.0, 1.0, 1.0, 0.0, 1.0)
+    cap = 8  # blocks a wave holds for 16x16 blocks
+
+    def sim():
+        s = F.Sim(ctx, FLIP, L, L, prm, b=16, n_colours=2, dt=0.1, T=100.0, split=0, seed=0, replica=9)
+        s.set_lattice(lat0)
+        return s
+
+    ref = sim()
+    ref.advance(4 * chunk)
+    want = (hashlib.sha256(ref.lattice().tobytes()).hexdigest(), ref.observe()["events"])
+    ref.close()
+    s = sim()
+    F.fskmc_ctx_set_persistent(ctx, chunk)
+    F.fskmc_ctx_set_rebalance(ctx, 1)
+    NBX = L // 16
+    colours = [((m % NBX) + (m // NBX)) % 2 for m in range(NBX * NBX)]  # Lie: window w has colour w % 2
+    active = [(chunk + 1) // 2, chunk // 2]  # windows of each colour in a launch starting at an even window
+    try:
+        prev = s.workload()
+        assert not prev.any()
+        cost = [1] * s.nb
+        for k in range(4):
+            s.advance(chunk)
+            part = s.last_partition()
+            now = s.workload()
+            waves = len(part) - 1
+            use = min(waves, max((s.nb + 1) // 2, -(-s.nb // cap)))
+            expect = balance.cdf_partition(cost, use, cap) + [s.nb] * (waves - use)
+            assert part.tolist() == expect, k
+            W, prev = now - prev, now
+            act = active if (k * chunk) % 2 == 0 else active[::-1]
+            cost = balance.block_costs(W.tolist(), colours, act, 3)
+            if k == 0:
+                first = W.copy()
+        got = (hashlib.sha256(s.lattice().tobytes()).hexdigest(), s.observe()["events"])
+    finally:
+        F.fskmc_ctx_set_rebalance(ctx, 0)
+        F.fskmc_ctx_set_persistent(ctx, 0)
+        s.close()
+    assert got == want
+    half = len(first) // 2
+    assert first[:half].sum() > 10 * first[half:].sum()  # the first histogram is strongly unbalanced

@@ -6,8 +6,9 @@
   workload is within max W of the best contiguous split found by brute force;
 * the paper's picture: with a coverage gradient the busy cells are spread
   over more processors (fewer cells each) than the idle ones;
-* with a capacity, ranges never exceed it, still tile the blocks, and equal
-  the unconstrained map whenever that already respects the capacity;
+* with a capacity, ranges never exceed it, still tile the blocks, equal the
+  unconstrained map whenever that already respects the capacity, and pack an
+  idle stretch at full capacity;
 * a histogram without mass splits as a uniform one.
 """
 import itertools
@@ -81,9 +82,25 @@ def test_capacity_respected_and_neutral_when_slack():
             assert b == free
 
 
+def test_capacity_packs_idle_stretch():
+    """Half the blocks idle (cost 1), half busy (cost 100), 4 processors per
+    8 blocks of capacity 4: the idle half is packed 4 per processor and the
+    busy half gets the remaining processors."""
+    W = [1] * 64 + [100] * 64
+    b = balance.cdf_partition(W, 32, 8)
+    sizes = [y - x for x, y in zip(b, b[1:])]
+    idle = [s for s, x in zip(sizes, b) if x < 64]
+    assert max(sizes) <= 8 and all(s == 8 for s in idle[:-1])
+    assert len(idle) <= 9
+
+
 def test_no_mass_is_uniform_and_errors():
     assert balance.cdf_partition([0] * 12, 4) == [0, 3, 6, 9, 12]
     with pytest.raises(ValueError):
         balance.cdf_partition([1] * 10, 2, cap=4)  # 10 blocks do not fit 2 x 4
     with pytest.raises(ValueError):
         balance.cdf_partition([1, -1], 1)
+
+
+def test_block_costs():
+    assert balance.block_costs([5, 0, 2], [0, 1, 0], [13, 12], 3) == [44, 36, 41]
