@@ -140,7 +140,8 @@ def bench_plain(F, ctx, wl, steps, warmup, stride, persist=0, resident=False, wp
         launches = sum(-(-o["window"] // persist) for o in obs)
         kname = (f"k_sweep_{'resident' if resident else 'persistent'}<P={P},{wl['kind']}> "
                  f"({persist} windows per launch)")
-        symbol = f"k_sweep_resident<{P}, {wl['b']}, {wl['b']}, {1 if wpg == 1 else 2}, 4>" if resident else None
+        cap = 4 if P == 16 else 8  # blocks a resident wave can hold
+        symbol = f"k_sweep_resident<{P}, {wl['b']}, {wl['b']}, {1 if wpg == 1 else 2}, {cap}>" if resident else None
     else:
         launches = sum(o["window"] for o in obs)
         kname = f"k_sweep_single<P={P},{wl['kind']}>"
