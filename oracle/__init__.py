@@ -29,6 +29,7 @@ _LIB_OVERRIDE = os.environ.get("FSKMC_ORACLE_LIB")
 
 MODEL_FLIP = 1
 MODEL_ZGB = 2
+MODEL_KAW = 3
 LIE, STRANG, RANDOM = 0, 1, 2
 
 GCC_FLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
@@ -111,6 +112,9 @@ class Model:
         elif kind == "zgb":
             vals = [params.get("y", 0.5), params.get("k_r", 1000.0), params.get("D", 0.0), 0.0, 0.0]
             code = MODEL_ZGB
+        elif kind == "kawasaki":
+            vals = [params.get("D", 1.0), params.get("J", 0.0), params.get("beta", 1.0), 0.0, 0.0]
+            code = MODEL_KAW
         else:
             raise ValueError(kind)
         self.params = vals
@@ -126,7 +130,7 @@ class Model:
 
     @property
     def n_states(self):
-        return 2 if self.kind == "flip" else 3
+        return 3 if self.kind == "zgb" else 2
 
 
 def philox(ctr, key):
@@ -154,7 +158,7 @@ def site_rate(model, lattice, site):
 
 
 def rate_table(model):
-    n = 243 * 14 if model.kind == "zgb" else 2 * (model.z + 1)
+    n = 2 * (model.z + 1) if model.kind == "flip" else 243 * 14
     out = np.zeros(n, np.float64)
     r = lib().or_rate_table(ctypes.byref(model._c), _ptr(out, ctypes.c_double), n)
     assert r == n, r

@@ -92,7 +92,9 @@ def _neighbours(Lx, Ly, dim, site):
 def events(kind, params, Lx, Ly, conf):
     """All events (x, rate, new configuration) of eq. generator for one
     configuration (a tuple of states).  kind 'flip': params (k_a,k_d,J,h,beta);
-    kind 'zgb': params (y,k_r,D)."""
+    kind 'zgb': params (y,k_r,D); kind 'kawasaki': params (D,J,beta), a
+    particle at x moves to an empty neighbour q (spin exchange) at rate
+    D/4 exp(-beta J n), n = occupied neighbours of x."""
     dim = 1 if Ly == 1 else 2
     N = Lx * Ly
     ev = []
@@ -109,6 +111,16 @@ def events(kind, params, Lx, Ly, conf):
             new = list(conf)
             new[x] = 1 - s
             ev.append((x, r, tuple(new)))
+        elif kind == "kawasaki":
+            D, J, beta = params
+            if s != 1:
+                continue
+            n = sum(1 for q in nb if conf[q] == 1)
+            for q in nb:
+                if conf[q] == 0:
+                    new = list(conf)
+                    new[x], new[q] = 0, 1
+                    ev.append((x, D / 4.0 * np.exp(-beta * J * n), tuple(new)))
         else:
             y_, kr, D = params
             if s == 0:
@@ -157,7 +169,7 @@ def generator(kind, params, Lx, Ly, owner=None, sparse=False):
     """Generator matrix Q[i,j] = rate(i -> j), Q[i,i] = -sum.  ``owner`` is an
     optional boolean array over sites: only events whose site x is owned count
     (the restriction of L to one colour, eq. opdecomp)."""
-    K = 2 if kind == "flip" else 3
+    K = 3 if kind == "zgb" else 2
     N = Lx * Ly
     S = K ** N
     rows, cols, vals = [], [], []
@@ -216,7 +228,7 @@ def site_owner_by_colour(Lx, Ly, bx, by, cmap, colour):
 def observable_vectors(kind, Lx, Ly):
     """Per-configuration observables matching the oracle's count layout:
     [#0, #1, #2, #bonds 0-0, #bonds 1-1, #bonds 2-2, #bonds A-B]."""
-    K = 2 if kind == "flip" else 3
+    K = 3 if kind == "zgb" else 2
     N = Lx * Ly
     dim = 1 if Ly == 1 else 2
     out = []

@@ -46,6 +46,7 @@
 
 #define OR_MODEL_FLIP 1
 #define OR_MODEL_ZGB 2
+#define OR_MODEL_KAW 3
 
 #define OR_LIE 0
 #define OR_STRANG 1
@@ -153,10 +154,10 @@ double or_log(double u)
  * Sites are indexed y*Lx + x on a periodic Lx x Ly lattice (Ly = 1 in 1D).
  * Directions: d=0 (+x), d=1 (-x), d=2 (+y), d=3 (-y); 1D uses d=0,1.        */
 typedef struct {
-    int model;   /* OR_MODEL_FLIP or OR_MODEL_ZGB */
+    int model;   /* OR_MODEL_FLIP, OR_MODEL_ZGB or OR_MODEL_KAW */
     int dim;     /* 1 or 2 */
     int Lx, Ly;
-    double p[5]; /* flip: k_a, k_d, J, h, beta.  zgb: y, k_r, D */
+    double p[5]; /* flip: k_a, k_d, J, h, beta.  zgb: y, k_r, D.  kaw: D, J, beta */
 } or_model;
 
 static int or_ndir(const or_model* M) { return M->dim == 1 ? 2 : 4; }
@@ -215,6 +216,34 @@ static void or_zgb_channels(const or_model* M, const uint8_t* lat, int site, dou
     }
 }
 
+/* Conserved spin exchange (Sec. 2, the diffusion example: Kawasaki dynamics,
+ * states 0 empty, 1 particle).  A particle at x hops to an empty nearest
+ * neighbour x+e_d with the Arrhenius rate (D/4) exp(-(beta * (J * n))), n =
+ * the number of occupied neighbours of x.  The hops use the reaction model's
+ * channel slots ch9+d (same order), every other channel is 0.              */
+static void or_kaw_channels(const or_model* M, const uint8_t* lat, int site, double ch[OR_ZGB_NCH])
+{
+    double D = M->p[0], J = M->p[1], beta = M->p[2];
+    int n = 0, d;
+    for (d = 0; d < OR_ZGB_NCH; d++)
+        ch[d] = 0.0;
+    if (lat[site] != 1)
+        return;
+    for (d = 0; d < 4; d++)
+        n += lat[or_neighbour(M, site, d)] == (OR_PLANT == 12 ? 0 : 1);
+    for (d = 0; d < 4; d++)
+        if (lat[or_neighbour(M, site, d)] == 0)
+            ch[9 + d] = (D / 4.0) * exp(-(beta * (J * (double)n)));
+}
+
+static void or_channels(const or_model* M, const uint8_t* lat, int site, double ch[OR_ZGB_NCH])
+{
+    if (M->model == OR_MODEL_KAW)
+        or_kaw_channels(M, lat, site, ch);
+    else
+        or_zgb_channels(M, lat, site, ch);
+}
+
 static double or_zgb_total(const double ch[OR_ZGB_NCH])
 {
     double tot = 0.0;
@@ -231,7 +260,7 @@ double or_site_rate(const or_model* M, const uint8_t* lat, int site)
         return or_flip_rate(M, lat, site);
     {
         double ch[OR_ZGB_NCH];
-        or_zgb_channels(M, lat, site, ch);
+        or_channels(M, lat, site, ch);
         return or_zgb_total(ch);
     }
 }
@@ -250,7 +279,7 @@ static int or_apply_event(const or_model* M, uint8_t* lat, int site, double tg, 
     } else {
         double ch[OR_ZGB_NCH];
         int c, pick = -1, last = -1, d, y;
-        or_zgb_channels(M, lat, site, ch);
+        or_channels(M, lat, site, ch);
         for (c = 0; c < OR_ZGB_NCH; c++) {
             if (ch[c] == 0.0)
                 continue;
@@ -325,7 +354,7 @@ int or_rate_table(const or_model* M, double* out, int n)
             lat[3] = (uint8_t)(r % 3); r /= 3;
             lat[7] = (uint8_t)(r % 3); r /= 3;
             lat[1] = (uint8_t)(r % 3);
-            or_zgb_channels(&T, lat, 4, ch);
+            or_channels(&T, lat, 4, ch);
             for (c = 0; c < OR_ZGB_NCH; c++)
                 out[pat * 14 + c] = ch[c];
             out[pat * 14 + 13] = or_zgb_total(ch);
@@ -499,7 +528,7 @@ int or_ssa_serial(const or_model* M, uint8_t* lat, double T, uint32_t seed, uint
  * gendecomp): no block of a colour may write a site another block of the same
  * colour reads or writes.  Flip models write C_m and read C_m + N(C_m);
  * pair models read and write C_m + N(C_m).                                   */
-static int or_is_pair_model(const or_model* M) { return M->model == OR_MODEL_ZGB; }
+static int or_is_pair_model(const or_model* M) { return M->model == OR_MODEL_ZGB || M->model == OR_MODEL_KAW; }
 
 int or_decomp_check(const or_model* M, int bx, int by, int n_colours, const int* colour_map)
 {

@@ -7,7 +7,7 @@ from oracle import exact
 
 
 def delta_state(kind, lattice):
-    K = 2 if kind == "flip" else 3
+    K = 3 if kind == "zgb" else 2
     p0 = np.zeros(K ** len(lattice))
     p0[exact.state_index(tuple(int(v) for v in lattice), K)] = 1.0
     return p0

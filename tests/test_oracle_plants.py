@@ -2,7 +2,7 @@
 plausible mistake (a wrong sign, a dropped guard, a wrong neighbour index, a
 wrong half step, a wrong factor, a missing colour test, a wrong constant, a
 wrong key schedule, a transposed direction, a colour
-drawn at the wrong rate, an off-by-one quantile) must fail at least one pin.
+drawn at the wrong rate, an off-by-one quantile, a wrong neighbour count) must fail at least one pin.
 
 Each variant is compiled on the CPU into a temporary library and the relevant
 pin tests are run against it in a child process."""
@@ -40,6 +40,8 @@ PLANTS = {
           "test_oracle_fs.py::test_fs_random_schedule_matches_averaged_propagator"]),
     11: ("workload quantile one block late (strict instead of non-strict CDF test)",
          ["test_oracle_balance.py"]),
+    12: ("exchange barrier counting the empty neighbours instead of the occupied ones",
+         ["test_oracle_kawasaki.py::test_serial_matches_master_equation"]),
 }
 
 
