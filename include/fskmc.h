@@ -53,8 +53,10 @@ typedef struct fskmc_sim fskmc_sim; /* one lattice replica / job            */
 /* Models (Sec. 2 examples; Sec. 7 eq. Arrhenius; Sec. 7.1 Table COrates). */
 typedef enum {
     FSKMC_MODEL_FLIP = 1, /* Arrhenius adsorption/desorption spin flip, states {0,1} */
-    FSKMC_MODEL_ZGB = 2   /* A adsorption, B2 dissociative adsorption, A+B reaction,
+    FSKMC_MODEL_ZGB = 2,  /* A adsorption, B2 dissociative adsorption, A+B reaction,
                              A hopping; states {0,1=A,2=B}; pair events              */
+    FSKMC_MODEL_KAWASAKI = 3 /* conserved spin exchange (Arrhenius surface diffusion),
+                                states {0,1}; pair events; two-dimensional only      */
 } fskmc_model;
 
 /* Processor communication schedules (Sec. 3, eqs. PCSl, PCSs, SLPCS). */
@@ -83,6 +85,14 @@ typedef struct {
 typedef struct {
     double y, k_r, D;
 } fskmc_zgb_params;
+
+/* Spin-exchange rates (Sec. 2, the conserved-dynamics example with the
+ * Arrhenius barrier of Sec. 7 eq. Arrhenius): a particle at x moves to an
+ * empty neighbour x+e_d at (D/4) * exp(-(beta * J * n)), n = #occupied
+ * neighbours of x.  The particle number is invariant.  D >= 0; J, beta finite. */
+typedef struct {
+    double D, J, beta;
+} fskmc_kawasaki_params;
 
 /* Decomposition (Sec. 2.1): blocks of bx x by sites tile the lattice; block
  * m = bj*(Lx/bx) + bi.  colour_map (length #blocks, values in [0, n_colours))
@@ -136,8 +146,8 @@ const char* fskmc_last_error(void);
  * decomposition (FSKMC_EDECOMP if two blocks of one colour can interact:
  * spin flip writes C_m and reads C_m plus its neighbours; pair models read
  * and write C_m plus its neighbours), builds the window schedule and
- * allocates the device state.  params points at fskmc_flip_params or
- * fskmc_zgb_params.  The lattice starts empty (all zeros). */
+ * allocates the device state.  params points at fskmc_flip_params,
+ * fskmc_zgb_params or fskmc_kawasaki_params.  The lattice starts empty (all zeros). */
 int fskmc_sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const void* params,
                      const fskmc_decomp* decomp, const fskmc_schedule* schedule, fskmc_key key,
                      fskmc_sim** out);

@@ -98,8 +98,10 @@ def _ptr(a, ct):
 
 class Model:
     """A lattice model: 'flip' (Arrhenius adsorption/desorption, Sec. 7 eq.
-    Arrhenius) with params (k_a, k_d, J, h, beta), or 'zgb' (Sec. 7.1, Table
-    COrates) with params (y, k_r, D)."""
+    Arrhenius) with params (k_a, k_d, J, h, beta), 'zgb' (Sec. 7.1, Table
+    COrates) with params (y, k_r, D), or 'kawasaki' (conserved spin exchange,
+    Sec. 2 example, Arrhenius barrier of the moving particle) with params
+    (D, J, beta)."""
 
     def __init__(self, kind, Lx, Ly=1, dim=None, **params):
         self.kind = kind

@@ -171,13 +171,20 @@ int kernel_shape(const fskmc_lattice& L, int model, int bx, int by, int* P, int*
         *shape = SHAPE_SQ;
     } else {
         if (model != FSKMC_MODEL_FLIP)
-            return fail(FSKMC_EINVAL, "the reaction model is two-dimensional");
+            return fail(FSKMC_EINVAL, "the pair-event models are two-dimensional");
         if (by != 1 || (bx != 64 && bx != 256 && bx != 1024))
             return fail(FSKMC_EINVAL, "1D blocks must be 64, 256 or 1024 sites (got %dx%d)", bx, by);
         *P = bx / 64;
         *shape = SHAPE_ROW;
     }
     return FSKMC_OK;
+}
+
+// Kernel family of a model: spin flip, or the table-driven pair-event sweep
+// (the reaction model and spin exchange share it; only the table differs).
+inline int kernel_model(int model)
+{
+    return model == FSKMC_MODEL_FLIP ? MODEL_FLIP : MODEL_ZGB;
 }
 
 // Neighbour of a site in direction d (0 +x, 1 -x, 2 +y, 3 -y), periodic.
@@ -202,7 +209,7 @@ int check_decomposition(const fskmc_sim& S)
     const fskmc_lattice& L = S.lat;
     const int64_t N = n_sites(L);
     const int nd = L.dim == 1 ? 2 : 4;
-    const bool pair = S.model == FSKMC_MODEL_ZGB;
+    const bool pair = S.model != FSKMC_MODEL_FLIP;
     std::vector<int32_t> ownW((size_t)N), ownR((size_t)N);
     for (int c = 0; c < S.n_colours; ++c) {
         std::fill(ownW.begin(), ownW.end(), -1);
@@ -297,6 +304,30 @@ void build_table(fskmc_sim& S)
         for (int n = 0; n <= z; ++n) {
             S.table[n] = ka;
             S.table[(z + 1) + n] = kd * std::exp(-(beta * (J * (double)n + h)));
+        }
+    } else if (S.model == FSKMC_MODEL_KAWASAKI) {
+        // Exchange uses the hop channels 9..12 of the pair-event table; the
+        // barrier counts the occupied neighbours of the moving particle.
+        const double D = S.prm[0], J = S.prm[1], beta = S.prm[2];
+        S.table.assign(243 * 14, 0.0);
+        for (int pat = 0; pat < 243; ++pat) {
+            int r = pat;
+            const int s = r % 3;
+            r /= 3;
+            int nb[4], n = 0;
+            for (int d = 0; d < 4; ++d) {
+                nb[d] = r % 3;
+                r /= 3;
+                n += nb[d] == 1;
+            }
+            double* ch = &S.table[(size_t)pat * 14];
+            for (int d = 0; d < 4; ++d)
+                if (s == 1 && nb[d] == 0)
+                    ch[9 + d] = (D / 4.0) * std::exp(-(beta * (J * (double)n)));
+            double tot = 0.0;
+            for (int c = 0; c < 13; ++c)
+                tot = tot + ch[c];
+            ch[13] = tot;
         }
     } else {
         const double y = S.prm[0], kr = S.prm[1], D = S.prm[2];
@@ -438,7 +469,7 @@ int enqueue_window(fskmc_sim* S, uint64_t w)
     a.w = (uint32_t)w;
     a.dur = S->win_dur[w];
     const LaunchTiming tk = timing_begin(S->ctx);
-    HIP_TRY(launch_sweep_single(S->model, S->P, S->shape, S->ctx->wpg, a, S->ctx->stream, tk));
+    HIP_TRY(launch_sweep_single(kernel_model(S->model), S->P, S->shape, S->ctx->wpg, a, S->ctx->stream, tk));
     timing_end(S->ctx, tk);
     S->block_windows += (uint64_t)a.n_blocks;
     return FSKMC_OK;
@@ -476,7 +507,7 @@ int enqueue_persistent(fskmc_sim* S, uint64_t w0, uint64_t w1)
     a.n_waves = 0;
     a.wait_ticks = c->wait_ticks;
     const LaunchTiming tk = timing_begin(c);
-    HIP_TRY(launch_sweep_persistent(S->model, S->P, S->shape, c->wpg, a, S->max_per_colour, st, tk));
+    HIP_TRY(launch_sweep_persistent(kernel_model(S->model), S->P, S->shape, c->wpg, a, S->max_per_colour, st, tk));
     timing_end(c, tk);
     HIP_TRY(hipMemcpyAsync(c->h_abort, c->d_abort, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     for (uint64_t w = w0; w < w1; ++w) {
@@ -639,7 +670,7 @@ int check_abort(fskmc_ctx* c)
 void build_neighbours(const fskmc_sim& S, std::vector<int32_t>& nbr)
 {
     nbr.assign((size_t)S.nb * 8, -1);
-    const bool pair = S.model == FSKMC_MODEL_ZGB;
+    const bool pair = S.model != FSKMC_MODEL_FLIP;
     for (int m = 0; m < S.nb; ++m) {
         const int bi = m % S.NBX, bj = m / S.NBX;
         int k = 0;
@@ -864,7 +895,7 @@ int fskmc_sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, co
     int rc = validate_lattice(lattice);
     if (rc)
         return rc;
-    if (model != FSKMC_MODEL_FLIP && model != FSKMC_MODEL_ZGB)
+    if (model != FSKMC_MODEL_FLIP && model != FSKMC_MODEL_ZGB && model != FSKMC_MODEL_KAWASAKI)
         return fail(FSKMC_EINVAL, "unknown model %d", model);
     fskmc_sim* S = new fskmc_sim();
     S->ctx = ctx;
@@ -879,6 +910,15 @@ int fskmc_sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, co
             !std::isfinite(p->beta) || !std::isfinite(p->k_a) || !std::isfinite(p->k_d)) {
             delete S;
             return fail(FSKMC_EINVAL, "spin-flip rates must be finite and k_a, k_d >= 0");
+        }
+    } else if (model == FSKMC_MODEL_KAWASAKI) {
+        const fskmc_kawasaki_params* p = (const fskmc_kawasaki_params*)params;
+        S->prm[0] = p->D;
+        S->prm[1] = p->J;
+        S->prm[2] = p->beta;
+        if (!(p->D >= 0) || !std::isfinite(p->D) || !std::isfinite(p->J) || !std::isfinite(p->beta)) {
+            delete S;
+            return fail(FSKMC_EINVAL, "spin exchange needs D >= 0 and finite D, J, beta");
         }
     } else {
         const fskmc_zgb_params* p = (const fskmc_zgb_params*)params;
@@ -1064,7 +1104,7 @@ int fskmc_sim_set_lattice(fskmc_sim* S, const uint8_t* host, size_t n)
         return fail(FSKMC_EINVAL, "NULL argument");
     if (n != (size_t)n_sites(S->lat))
         return fail(FSKMC_EINVAL, "lattice has %lld sites, got %zu bytes", (long long)n_sites(S->lat), n);
-    const int K = S->model == FSKMC_MODEL_FLIP ? 2 : 3;
+    const int K = S->model == FSKMC_MODEL_ZGB ? 3 : 2;
     for (size_t i = 0; i < n; ++i)
         if (host[i] >= K)
             return fail(FSKMC_EINVAL, "site %zu has state %d outside [0,%d)", i, (int)host[i], K);
@@ -1255,10 +1295,10 @@ int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t 
             continue;
         Group* g = nullptr;
         for (auto& gg : groups)
-            if (gg.model == S->model && gg.P == S->P && gg.shape == S->shape)
+            if (gg.model == kernel_model(S->model) && gg.P == S->P && gg.shape == S->shape)
                 g = &gg;
         if (!g) {
-            groups.push_back(Group{S->model, S->P, S->shape, {}, 0, 0, 0});
+            groups.push_back(Group{kernel_model(S->model), S->P, S->shape, {}, 0, 0, 0});
             g = &groups.back();
         }
         g->idx.push_back(i);

@@ -13,7 +13,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfskmc.so")
 
 FSKMC_OK, FSKMC_EINVAL, FSKMC_ENOMEM, FSKMC_EDEVICE, FSKMC_EDECOMP, FSKMC_EBUSY, FSKMC_ESTATE = 0, -1, -2, -3, -4, -5, -6
-FSKMC_MODEL_FLIP, FSKMC_MODEL_ZGB = 1, 2
+FSKMC_MODEL_FLIP, FSKMC_MODEL_ZGB, FSKMC_MODEL_KAWASAKI = 1, 2, 3
+MODELS = {"flip": FSKMC_MODEL_FLIP, "zgb": FSKMC_MODEL_ZGB, "kawasaki": FSKMC_MODEL_KAWASAKI}
 FSKMC_LIE, FSKMC_STRANG, FSKMC_RANDOM = 0, 1, 2
 
 ERRORS = {FSKMC_EINVAL: "EINVAL", FSKMC_ENOMEM: "ENOMEM", FSKMC_EDEVICE: "EDEVICE", FSKMC_EDECOMP: "EDECOMP",
@@ -37,6 +38,10 @@ class fskmc_flip_params(ctypes.Structure):
 
 class fskmc_zgb_params(ctypes.Structure):
     _fields_ = [("y", ctypes.c_double), ("k_r", ctypes.c_double), ("D", ctypes.c_double)]
+
+
+class fskmc_kawasaki_params(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_double), ("J", ctypes.c_double), ("beta", ctypes.c_double)]
 
 
 class fskmc_decomp(ctypes.Structure):
@@ -210,6 +215,8 @@ def fskmc_sim_create(ctx, dim, Lx, Ly, model, params, bx, by, n_colours, dt, T, 
     lat = fskmc_lattice(dim, Lx, Ly)
     if model == FSKMC_MODEL_FLIP:
         p = fskmc_flip_params(*params)
+    elif model == FSKMC_MODEL_KAWASAKI:
+        p = fskmc_kawasaki_params(*params)
     else:
         p = fskmc_zgb_params(*params)
     dec, _keep = _decomp(bx, by, n_colours, colour_map)
@@ -305,7 +312,8 @@ def fskmc_batch_advance(ctx, sims, windows):
 class Sim:
     """One lattice simulation on the GPU.
 
-    kind 'flip': params (k_a, k_d, J, h, beta); kind 'zgb': params (y, k_r, D).
+    kind 'flip': params (k_a, k_d, J, h, beta); kind 'zgb': params (y, k_r, D);
+    kind 'kawasaki': params (D, J, beta).
     """
 
     def __init__(self, ctx, kind, Lx, Ly=1, params=(1.0, 1.0, 0.0, 0.0, 1.0), b=None, bx=None, by=None,
@@ -318,7 +326,9 @@ class Sim:
             bx, by = (b, b) if self.dim == 2 else (b, 1)
         self.bx, self.by = bx, by
         self.n_colours = n_colours
-        self.model = FSKMC_MODEL_FLIP if kind == "flip" else FSKMC_MODEL_ZGB
+        if kind not in MODELS:
+            raise ValueError(f"unknown model kind {kind!r}")
+        self.model = MODELS[kind]
         self.handle = fskmc_sim_create(ctx, self.dim, Lx, Ly, self.model, params, bx, by, n_colours, dt, T, split,
                                        seed, replica, colour_map)
         self.N = Lx * Ly

@@ -14,6 +14,7 @@ pytestmark = pytest.mark.gpu
 
 FLIP = "flip"
 ZGB = "zgb"
+KAW = "kawasaki"
 
 
 @pytest.fixture(scope="module")
@@ -33,6 +34,9 @@ def _orc_model(orc, kind, Lx, Ly, params):
     if kind == FLIP:
         k_a, k_d, J, h, beta = params
         return orc.Model(FLIP, Lx, Ly, k_a=k_a, k_d=k_d, J=J, h=h, beta=beta)
+    if kind == KAW:
+        D, J, beta = params
+        return orc.Model(KAW, Lx, Ly, D=D, J=J, beta=beta)
     y, k_r, D = params
     return orc.Model(ZGB, Lx, Ly, y=y, k_r=k_r, D=D)
 
@@ -108,7 +112,8 @@ class Pair:
 def test_rate_tables_bitwise(F, orc, ctx):
     cases = [(FLIP, 64, 64, (1.0, 1.0, 1.0, 0.0, 1.0), 8, 2), (FLIP, 256, 1, (0.3, 2.5, 2.0, -1.0, 1.7), 64, 2),
              (FLIP, 64, 64, (1.0, 1.0, 0.5, 0.3, 3.0), 16, 2), (ZGB, 64, 64, (0.53, 1000.0, 10.0), 32, 4),
-             (ZGB, 64, 64, (0.3, 7.5, 0.0), 16, 4)]
+             (ZGB, 64, 64, (0.3, 7.5, 0.0), 16, 4), (KAW, 64, 64, (4.0, 1.0, 1.0), 16, 4),
+             (KAW, 64, 64, (1.0, -0.7, 2.0), 32, 4), (KAW, 64, 64, (0.0, 0.0, 1.0), 8, 4)]
     for kind, Lx, Ly, prm, b, ncol in cases:
         p = Pair(F, orc, ctx, kind, Lx, Ly, prm, b, ncol, 0.1, 0.2, "lie")
         got = p.sim.rate_table()
@@ -212,6 +217,30 @@ def test_reaction_model_small_blocks(F, orc, ctx, b):
     p.step_compare_each(14)
 
 
+@pytest.mark.parametrize("D,J,split,b", [(4.0, 1.0, "strang", 32), (4.0, -0.5, "lie", 16), (2.0, 2.0, "random", 8),
+                                         (4.0, 0.0, "strang", 32)],
+                         ids=["repulsive-strang-b32", "attractive-lie-b16", "random-b8", "exclusion-b32"])
+def test_kawasaki_every_window(F, orc, ctx, D, J, split, b):
+    """Conserved spin exchange: particles hop into the halo of the block, 4
+    colours; every window bit-exact, the particle number invariant."""
+    p = Pair(F, orc, ctx, KAW, 256, 256, (D, J, 1.0), b, 4, 0.25, 20.0, split, init="bernoulli", seed=2, replica=b)
+    n0 = int(p.lat.sum())
+    assert p.step_compare_each(14) > 0
+    p.step_compare_end(14)
+    obs = p.sim.observe()
+    want = orc.observe(p.model, p.lat)
+    assert obs["count"][1] == n0 and obs["count"][2] == 0
+    assert obs["count"] == list(want[:3]) and obs["bonds_equal"] == list(want[3:6])
+
+
+def test_kawasaki_full_size_first_windows(F, orc, ctx):
+    """4096^2 half-filled exchange lattice, 32x32 blocks, Strang: the first
+    two windows compared in full."""
+    p = Pair(F, orc, ctx, KAW, 4096, 4096, (4.0, 1.0, 1.0), 32, 4, 0.05, 10.0, "strang", init="bernoulli",
+             seed=0, replica=0)
+    p.step_compare_each(2)
+
+
 def test_config2_full_size_first_windows(F, orc, ctx):
     """4096^2 reaction lattice, 32x32 blocks, Strang dt=0.05: the first two
     windows compared in full."""
@@ -252,6 +281,20 @@ def test_edge_invalid_inputs(F, ctx):
         F.Sim(ctx, FLIP, 60, 60, (1, 1, 1, 0, 1), b=12, dt=0.1, T=1.0)
     with pytest.raises(E):  # odd number of blocks breaks the 2-colour checkerboard
         F.Sim(ctx, FLIP, 24, 24, (1, 1, 1, 0, 1), b=8, dt=0.1, T=1.0)
+    with pytest.raises(E) as ei:  # spin exchange is a pair model: no 2-colour checkerboard
+        F.Sim(ctx, KAW, 64, 64, (1.0, 1.0, 1.0), b=16, n_colours=2, dt=0.1, T=1.0)
+    assert ei.value.code == F.FSKMC_EDECOMP
+    with pytest.raises(E) as ei:  # pair models are two-dimensional
+        F.Sim(ctx, KAW, 1024, 1, (1.0, 1.0, 1.0), b=64, n_colours=2, dt=0.1, T=1.0)
+    assert ei.value.code == F.FSKMC_EINVAL
+    for bad in ((-1.0, 1.0, 1.0), (1.0, float("inf"), 1.0), (1.0, 1.0, float("nan"))):
+        with pytest.raises(E) as ei:
+            F.Sim(ctx, KAW, 64, 64, bad, b=16, n_colours=4, dt=0.1, T=1.0)
+        assert ei.value.code == F.FSKMC_EINVAL
+    k = F.Sim(ctx, KAW, 64, 64, (1.0, 1.0, 1.0), b=16, n_colours=4, dt=0.1, T=0.1)
+    with pytest.raises(E):  # exchange has states {0, 1} only
+        k.set_lattice(np.full(4096, 2, np.uint8))
+    k.close()
     s = F.Sim(ctx, FLIP, 64, 64, (1, 1, 1, 0, 1), b=8, dt=0.1, T=0.1)
     with pytest.raises(E):  # state outside the spin space
         s.set_lattice(np.full(4096, 2, np.uint8))
@@ -320,6 +363,8 @@ def test_batch_equals_alone(F, orc, ctx):
              seed=0, replica=4),
         dict(kind=FLIP, Lx=512, Ly=1, params=(1.0, 1.0, 1.0, 0.0, 1.0), b=64, n_colours=2, dt=1.0, T=5.0,
              split=0, seed=0, replica=5),
+        dict(kind=KAW, Lx=128, Ly=128, params=(4.0, 1.0, 1.0), b=32, n_colours=4, dt=0.25, T=3.0, split=1,
+             seed=0, replica=6),
     ]
     alone, batch = [], []
     for sp in specs:
@@ -348,8 +393,9 @@ def test_batch_equals_alone(F, orc, ctx):
     (ZGB, 256, 256, (0.5, 1000.0, 10.0), 32, 4, 0.05, 10.0, "strang", "empty", 11),
     (FLIP, 16, 16, (1.0, 1.0, 1.0, 0.2, 1.0), 8, 2, 0.5, 20.0, "strang", "bernoulli", 6),
     (FLIP, 128, 1, (1.0, 1.0, 1.5, 0.0, 1.0), 64, 2, 1.0, 50.0, "random", "bernoulli", 13),
+    (KAW, 256, 256, (4.0, 1.0, 1.0), 32, 4, 0.25, 20.0, "strang", "bernoulli", 9),
 ], ids=["flip64-b8", "flip256-b16-strang", "flip256-b32-random", "flip1d-b256", "zgb256-b32", "flip16-b8-2x2",
-        "flip1d-128-b64-two-blocks"])
+        "flip1d-128-b64-two-blocks", "kawasaki256-b32"])
 @pytest.mark.parametrize("resident", [1, 0], ids=["resident", "streaming"])
 def test_persistent_sweep_bitwise(F, orc, ctx, case, resident):
     """Several windows inside one persistent kernel (neighbour-only waits
