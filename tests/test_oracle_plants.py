@@ -42,6 +42,8 @@ PLANTS = {
          ["test_oracle_balance.py"]),
     12: ("exchange barrier counting the empty neighbours instead of the occupied ones",
          ["test_oracle_kawasaki.py::test_serial_matches_master_equation"]),
+    13: ("nested inner schedule spanning dt instead of the outer window's length",
+         ["test_oracle_nested.py::test_window_lists_by_hand"]),
 }
 
 
