@@ -32,7 +32,13 @@ Also in the JSON line:
   balance       workload rebalancing (Sec. 5) on a half-filled 2048^2
                 lattice: one launch per window, resident launches on fixed
                 block ranges and on ranges rebalanced from the previous
-                launch's workload histogram, bit-identity checked.
+                launch's workload histogram, bit-identity checked;
+  nested        the nested decomposition (Sec. 6) of the 1024^2 lattice
+                (coarse cells of 4x4 blocks, outer Lie dt=0.1, inner Lie
+                dtau=0.05): one launch per outer window with a workgroup per
+                coarse cell, against the flat sweeps (one launch per window,
+                and one persistent launch) on the same window list,
+                bit-identity checked.
 """
 import argparse
 import json
@@ -289,6 +295,53 @@ def bench_balance(F, ctx, windows, chunk):
     return out
 
 
+def bench_nested(F, ctx, T, dtau, c, stride):
+    """Nested decomposition (Sec. 6) of the 1024^2 lattice, whole runs to T:
+    the nested kernel (one launch per outer window), the flat per-window
+    sweep and the flat persistent sweep on the same window list."""
+    import hashlib
+    from paper_1105_4673_amd import workloads
+    wl = workloads.nested(c=c, dtau=dtau, T=T)
+    out = {"workload": wl["name"]}
+    digests = []
+    for label, knob, persist in (("nested_kernel", 1, 0), ("flat_per_window", 0, 0), ("flat_persistent", 0, 100000)):
+        F.fskmc_ctx_set_nested(ctx, knob)
+        F.fskmc_ctx_set_persistent(ctx, persist)
+        best = None
+        for rep in range(2):  # the first pass also warms the kernels up
+            s = F.Sim(ctx, wl["kind"], wl["Lx"], wl["Ly"], wl["params"], b=wl["b"], dt=wl["dt"], T=wl["T"],
+                      split=wl["split"], seed=0, replica=11, nested=wl["nested"])
+            init_sim(s, wl)
+            F.fskmc_sync(ctx)
+            if knob:
+                F.fskmc_ctx_set_kernel_timing(ctx, stride)
+            t0 = time.perf_counter()
+            s.run_to_end()
+            F.fskmc_sync(ctx)
+            el = time.perf_counter() - t0
+            if knob:
+                kms, kn = F.fskmc_ctx_read_kernel_timing(ctx)
+                F.fskmc_ctx_set_kernel_timing(ctx, 0)
+            obs = s.observe()
+            dig = hashlib.sha256(s.lattice().tobytes()).hexdigest()
+            launches = s.windows()[0]
+            s.close()
+            if best is None or el < best[0]:
+                best = (el, obs["events"], kms / max(kn, 1) if knob else None)
+        el, ev, kavg = best
+        out[label] = {"value": ev / el, "seconds": el, "events": ev}
+        if kavg is not None:
+            out[label]["kernel_ms_avg"] = kavg
+        digests.append(dig)
+        log(f"nested {label}: {ev / el:.3g} events/s ({el * 1e3:.1f} ms, {launches} windows)")
+    F.fskmc_ctx_set_nested(ctx, 1)
+    F.fskmc_ctx_set_persistent(ctx, 0)
+    out["bit_identical"] = len(set(digests)) == 1
+    out["speedup_vs_flat_per_window"] = out["nested_kernel"]["value"] / out["flat_per_window"]["value"]
+    out["speedup_vs_flat_persistent"] = out["nested_kernel"]["value"] / out["flat_persistent"]["value"]
+    return out
+
+
 def bench_served(F, ctx, rates, n_jobs, windows_per_step, budget_gib):
     """Poisson request streams of mixed Ising / reaction jobs served with
     continuous batching; time-to-result percentiles and aggregate events/s."""
@@ -338,6 +391,9 @@ def main():
     ap.add_argument("--balance-windows", type=int, default=200,
                     help="windows of the half-filled 2048^2 rebalancing comparison; 0 skips it")
     ap.add_argument("--balance-chunk", type=int, default=20)
+    ap.add_argument("--nested-T", type=float, default=20.0, help="0 skips the nested measurement")
+    ap.add_argument("--nested-dtau", type=float, default=0.05)
+    ap.add_argument("--nested-cell", type=int, default=4)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -411,6 +467,9 @@ def main():
         result["sweep"] = sweep
     if args.balance_windows:
         result["balance"] = bench_balance(F, ctx, args.balance_windows, args.balance_chunk)
+    if args.nested_T:
+        result["nested"] = bench_nested(F, ctx, args.nested_T, args.nested_dtau, args.nested_cell,
+                                        args.timing_stride)
     F.fskmc_ctx_set_persistent(ctx, 0)  # batched and served runs use one packed launch per window
     if args.batched_jobs:
         F.fskmc_ctx_set_waves_per_group(ctx, args.waves_per_group)

@@ -104,6 +104,26 @@ typedef struct {
     const int* colour_map;
 } fskmc_decomp;
 
+/* Nested (hierarchical) decomposition (Sec. 6, eqs. sublatt2 and opdecomp2).
+ * Coarse cells of cx x cy fine blocks (bx x by sites each) carry the outer
+ * colouring over coarse positions (I, J): 2 colours (I+J)%2, 4 colours
+ * (I%2)+2(J%2); inside a cell, fine blocks at (i, j) carry the inner colouring
+ * (2 or 4 colours, the same formulas).  The scheme applies the schedule's
+ * splitting (Lie or Strang, step dt) over the outer colours and replaces each
+ * outer window of length d by the inner splitting (Lie or Strang, step dtau)
+ * over the inner colours for time d; d / dtau must be an integer.  Fine block
+ * m gets colour outer * inner_colours + inner, and window w of the expanded
+ * list draws as in the flat scheme, so a nested sim gives the bits of a flat
+ * sim with that colour map and window list. */
+typedef struct {
+    int bx, by;        /* fine blocks (one GPU wave each); the shapes of fskmc_decomp */
+    int cx, cy;        /* fine blocks per coarse cell along x and y */
+    int outer_colours; /* 2 or 4 */
+    int inner_colours; /* 2 or 4 */
+    int inner_split;   /* FSKMC_LIE or FSKMC_STRANG */
+    double dtau;       /* inner step */
+} fskmc_nested;
+
 /* Schedule: window length dt and final time T (Sec. 2.2, T = n dt; T/dt must
  * be an integer to 1e-9 relative, else FSKMC_EINVAL). */
 typedef struct {
@@ -152,6 +172,22 @@ int fskmc_sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, co
                      const fskmc_decomp* decomp, const fskmc_schedule* schedule, fskmc_key key,
                      fskmc_sim** out);
 int fskmc_sim_destroy(fskmc_sim* sim);
+
+/* Create a simulation on a nested decomposition (see fskmc_nested); schedule
+ * gives the outer step dt, T and the outer splitting (Lie or Strang).  Two
+ * dimensions only.  FSKMC_EINVAL: cells that do not tile the block grid,
+ * colourings other than 2 or 4, a random splitting, an outer window that is
+ * not a whole number of inner steps.  FSKMC_EDECOMP: fewer than 2 x 2 coarse
+ * cells, coarse cells of one outer colour that interact (pair models need 4
+ * outer colours), or interacting fine blocks of one flat colour.  On a GPU,
+ * square cells of 2 x 2 or 4 x 4 blocks (spin flip, 2 inner colours; or 4 x 4
+ * blocks with 4; pair models 2 x 2 or 4 x 4 blocks with 4 inner colours) run
+ * one launch per outer window, one workgroup per coarse cell, every inner
+ * window inside it; other shapes, or fskmc_ctx_set_nested(ctx, 0), run the
+ * flat sweeps on the same window list (same bits). */
+int fskmc_sim_create_nested(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const void* params,
+                            const fskmc_nested* nested, const fskmc_schedule* schedule, fskmc_key key,
+                            fskmc_sim** out);
 
 /* Use caller-owned device memory (e.g. a torch uint8 tensor of Lx*Ly bytes)
  * as the lattice instead of the library's buffer.  The current lattice is
@@ -237,6 +273,14 @@ int fskmc_ctx_set_resident(fskmc_ctx* ctx, int on);
  * launches, over max(ceil(n_blocks/2), ceil(n_blocks/capacity)) waves (at most
  * the resident waves). */
 int fskmc_ctx_set_rebalance(fskmc_ctx* ctx, int on);
+
+/* Knob that never changes results (default on): nested simulations whose
+ * cells have a GPU variant advance one launch per outer window (one workgroup
+ * per coarse cell, the inner windows separated by workgroup barriers); off,
+ * they use the flat sweeps (one launch per window, or the persistent sweeps)
+ * on the same window list.  The persistent setting does not apply to the
+ * nested launches. */
+int fskmc_ctx_set_nested(fskmc_ctx* ctx, int on);
 
 /* Workload histogram (Sec. 5, eq. wload): out[m] = accepted events of block m
  * (block order m = bj*NBX + bi) since the last fskmc_sim_init, set_lattice or

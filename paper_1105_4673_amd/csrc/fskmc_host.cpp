@@ -88,6 +88,7 @@ struct fskmc_ctx {
     int persist = 0;
     bool resident = true;        // spin flip: keep blocks in LDS across the windows of a launch
     bool rebalance = false;      // resident launches: block ranges by the workload of the previous launch
+    bool nested_kernel = true;   // nested sims: one workgroup per coarse cell and outer window
     unsigned long long wait_ticks = 200000000ull; // longest neighbour wait: 2 s of the 100 MHz wall clock
     int32_t* d_abort = nullptr;  // raised by the persistent kernel on a timed-out wait
     int32_t* h_abort = nullptr;  // pinned copy, refreshed after each persistent launch
@@ -140,6 +141,16 @@ struct fskmc_sim {
     unsigned long long* d_scan = nullptr;
     int32_t* d_owner = nullptr;
     size_t n_owner = 0, cap_owner = 0;
+    // nested decomposition: coarse cells of cx x cy blocks (NCX per row),
+    // k_outer x k_inner colours, inner scheme of step dtau; coarse cells
+    // grouped by outer colour; per window, one past the last window of its
+    // outer window
+    bool nested = false, nest_kernel_ok = false;
+    int cx = 0, cy = 0, NCX = 0, NCY = 0, k_outer = 0, k_inner = 0, inner_split = 0;
+    double dtau = 0.0;
+    std::vector<int32_t> cells, cell_off;
+    std::vector<uint32_t> outer_end;
+    int32_t* d_cells = nullptr;
 };
 
 namespace {
@@ -246,50 +257,94 @@ int check_decomposition(const fskmc_sim& S)
     return FSKMC_OK;
 }
 
-int build_schedule(fskmc_sim& S)
+// Windows of one splitting scheme over K colours with step dt up to time T,
+// appended to (col, dur, end); w0 is the index of the first of them in the
+// whole list (the random schedule's Philox counter).
+int scheme_windows(int split, int K, double dt, double T, fskmc_key key, uint64_t w0, std::vector<int8_t>& col,
+                   std::vector<double>& dur, std::vector<uint8_t>& end)
 {
-    const double dt = S.sched.dt, T = S.sched.T;
     if (!(dt > 0.0) || !(T >= 0.0) || !std::isfinite(dt) || !std::isfinite(T))
         return fail(FSKMC_EINVAL, "need dt > 0 and T >= 0");
     const double nd = std::floor(T / dt + 0.5);
     if (std::fabs(nd * dt - T) > 1e-9 * std::max(1.0, T))
         return fail(FSKMC_EINVAL, "T / dt = %.17g is not an integer", T / dt);
-    if (S.sched.split != FSKMC_LIE && S.sched.split != FSKMC_STRANG && S.sched.split != FSKMC_RANDOM)
-        return fail(FSKMC_EINVAL, "unknown splitting %d", S.sched.split);
-    const int K = S.n_colours;
+    if (split != FSKMC_LIE && split != FSKMC_STRANG && split != FSKMC_RANDOM)
+        return fail(FSKMC_EINVAL, "unknown splitting %d", split);
     const int64_t steps = (int64_t)nd;
-    const int per = S.sched.split == FSKMC_STRANG ? 2 * K - 1 : K;
-    if (steps * per > ((int64_t)1 << 32) - 1)
+    const int per = split == FSKMC_STRANG ? 2 * K - 1 : K;
+    if ((int64_t)w0 + steps * per > ((int64_t)1 << 32) - 1)
         return fail(FSKMC_EINVAL, "more than 2^32 windows");
     const double half = 0.5 * dt;
-    S.win_colour.clear();
-    S.win_dur.clear();
-    S.step_end.clear();
-    S.win_colour.reserve((size_t)(steps * per));
-    S.win_dur.reserve((size_t)(steps * per));
-    uint32_t w = 0;
+    col.reserve(col.size() + (size_t)(steps * per));
+    dur.reserve(dur.size() + (size_t)(steps * per));
+    uint32_t w = (uint32_t)w0;
     for (int64_t k = 0; k < steps; ++k) {
         for (int i = 0; i < per; ++i, ++w) {
             int c;
             double d;
-            if (S.sched.split == FSKMC_LIE) {
+            if (split == FSKMC_LIE) {
                 c = i;
                 d = dt;
-            } else if (S.sched.split == FSKMC_STRANG) {
+            } else if (split == FSKMC_STRANG) {
                 c = i < K ? i : 2 * (K - 1) - i;
                 d = c == K - 1 ? dt : half;
             } else {
                 uint32_t ctr[4] = {w, 0u, 0u, 3u};
-                philox_host(ctr, S.key.seed, S.key.replica);
+                philox_host(ctr, key.seed, key.replica);
                 const uint64_t b = ((uint64_t)ctr[2] << 32) | ctr[3];
                 const double V = (double)(b >> 11) * 0x1p-53;
                 c = (int)(V * (double)K);
                 d = dt;
             }
-            S.win_colour.push_back((int8_t)c);
-            S.win_dur.push_back(d);
-            S.step_end.push_back(i == per - 1 ? 1 : 0);
+            col.push_back((int8_t)c);
+            dur.push_back(d);
+            end.push_back(i == per - 1 ? 1 : 0);
         }
+    }
+    return FSKMC_OK;
+}
+
+int build_schedule(fskmc_sim& S)
+{
+    S.win_colour.clear();
+    S.win_dur.clear();
+    S.step_end.clear();
+    int rc = scheme_windows(S.sched.split, S.n_colours, S.sched.dt, S.sched.T, S.key, 0, S.win_colour, S.win_dur,
+                            S.step_end);
+    S.n_windows = S.win_colour.size();
+    return rc;
+}
+
+// Nested scheme (Sec. 6, eqs. sublatt2 and opdecomp2): the outer scheme of
+// step dt over the outer colours, each outer window (c, d) replaced by the
+// inner scheme of step dtau over the inner colours for time d, on flat colour
+// c * k_inner + inner colour.  step_end marks the end of every outer step.
+int build_nested_schedule(fskmc_sim& S)
+{
+    if (S.sched.split == FSKMC_RANDOM || (S.inner_split != FSKMC_LIE && S.inner_split != FSKMC_STRANG))
+        return fail(FSKMC_EINVAL, "the nested scheme takes Lie or Strang at both levels");
+    std::vector<int8_t> oc;
+    std::vector<double> od;
+    std::vector<uint8_t> oe;
+    int rc = scheme_windows(S.sched.split, S.k_outer, S.sched.dt, S.sched.T, S.key, 0, oc, od, oe);
+    if (rc)
+        return rc;
+    S.win_colour.clear();
+    S.win_dur.clear();
+    S.step_end.clear();
+    S.outer_end.clear();
+    for (size_t k = 0; k < oc.size(); ++k) {
+        const size_t first = S.win_colour.size();
+        if ((rc = scheme_windows(S.inner_split, S.k_inner, S.dtau, od[k], S.key, first, S.win_colour, S.win_dur,
+                                 S.step_end)))
+            return fail(rc, "outer window of length %.17g is not a whole number of inner steps %.17g (%s)", od[k],
+                        S.dtau, fskmc_last_error());
+        for (size_t i = first; i < S.win_colour.size(); ++i) {
+            S.win_colour[i] = (int8_t)(oc[k] * S.k_inner + S.win_colour[i]);
+            S.step_end[i] = 0;
+        }
+        S.step_end.back() = oe[k];
+        S.outer_end.resize(S.win_colour.size(), (uint32_t)S.win_colour.size());
     }
     S.n_windows = S.win_colour.size();
     return FSKMC_OK;
@@ -391,6 +446,7 @@ void free_sim_device(fskmc_sim* S)
     (void)hipFree(S->d_prev);
     (void)hipFree(S->d_edge);
     (void)hipFree(S->d_owner);
+    (void)hipFree(S->d_cells);
     (void)hipFree(S->d_ev_prev);
     (void)hipFree(S->d_scan);
     S->d_lat = nullptr;
@@ -449,6 +505,34 @@ int reset_counters(fskmc_sim* S)
     S->block_windows = 0;
     S->have_prev = false;
     HIP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(S->d_cnt), 2 * (int64_t)S->nb, 0ull, st));
+    return FSKMC_OK;
+}
+
+// Inner windows [w0, w1) of one outer window of a nested sim: one launch,
+// one workgroup per coarse cell of the outer colour.
+int enqueue_nested(fskmc_sim* S, uint64_t w0, uint64_t w1)
+{
+    const int co = S->win_colour[w0] / S->k_inner;
+    NestedArgs a{};
+    a.lat = S->d_lat;
+    a.table = S->d_table;
+    a.cnt = S->d_cnt;
+    a.win_colour = S->d_wcol;
+    a.win_dur = S->d_wdur;
+    a.cells = S->d_cells + S->cell_off[co];
+    a.n_cells = S->cell_off[co + 1] - S->cell_off[co];
+    a.Lx = S->lat.Lx;
+    a.Ly = S->lat.Ly;
+    a.NBX = S->NBX;
+    a.NCX = S->NCX;
+    a.k0 = S->key.seed;
+    a.k1 = S->key.replica;
+    a.w0 = (int)w0;
+    a.w1 = (int)w1;
+    const LaunchTiming tk = timing_begin(S->ctx);
+    HIP_TRY(launch_sweep_nested(kernel_model(S->model), S->P, S->cx, S->k_inner, a, S->ctx->stream, tk));
+    timing_end(S->ctx, tk);
+    S->block_windows += (w1 - w0) * (uint64_t)a.n_cells * (uint64_t)(S->cx * S->cy / S->k_inner);
     return FSKMC_OK;
 }
 
@@ -843,6 +927,14 @@ int fskmc_ctx_set_resident(fskmc_ctx* c, int on)
     return FSKMC_OK;
 }
 
+int fskmc_ctx_set_nested(fskmc_ctx* c, int on)
+{
+    if (!c)
+        return fail(FSKMC_EINVAL, "ctx is NULL");
+    c->nested_kernel = on != 0;
+    return FSKMC_OK;
+}
+
 int fskmc_ctx_set_kernel_timing(fskmc_ctx* c, int stride)
 {
     if (!c)
@@ -886,8 +978,32 @@ int fskmc_sync(fskmc_ctx* c)
     return check_abort(c);
 }
 
-int fskmc_sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const void* params,
-                     const fskmc_decomp* decomp, const fskmc_schedule* schedule, fskmc_key key, fskmc_sim** out)
+// Independence of the coarse cells of one outer colour, as blocks of
+// (cx bx) x (cy by) sites (eq. opdecomp at the coarse level): the nested
+// scheme evolves them independently with their rings frozen.
+int check_coarse(const fskmc_sim& S)
+{
+    if (S.NCX < 2 || S.NCY < 2)
+        return fail(FSKMC_EDECOMP, "the nested decomposition needs at least 2 x 2 coarse cells (got %d x %d)", S.NCX,
+                    S.NCY);
+    fskmc_sim C;
+    C.lat = S.lat;
+    C.model = S.model;
+    C.bx = S.bx * S.cx;
+    C.by = S.by * S.cy;
+    C.NBX = S.NCX;
+    C.NBY = S.NCY;
+    C.nb = S.NCX * S.NCY;
+    C.n_colours = S.k_outer;
+    C.blocks = S.cells;
+    C.colour_off = S.cell_off;
+    const int rc = check_decomposition(C);
+    return rc ? fail(rc, "coarse cells of one outer colour interact: %s", fskmc_last_error()) : FSKMC_OK;
+}
+
+int sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const void* params,
+               const fskmc_decomp* decomp, const fskmc_schedule* schedule, fskmc_key key, const fskmc_nested* nest,
+               fskmc_sim** out)
 {
     if (!ctx || !out || !params || !decomp || !schedule)
         return fail(FSKMC_EINVAL, "NULL argument");
@@ -951,8 +1067,48 @@ int fskmc_sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, co
         delete S;
         return fail(FSKMC_EINVAL, "n_colours must be in [1,127]");
     }
+    if (nest) {
+        S->nested = true;
+        S->cx = nest->cx;
+        S->cy = nest->cy;
+        S->k_outer = nest->outer_colours;
+        S->k_inner = nest->inner_colours;
+        S->inner_split = nest->inner_split;
+        S->dtau = nest->dtau;
+        if (S->lat.dim != 2 || S->cx < 1 || S->cy < 1 || S->NBX % S->cx || S->NBY % S->cy) {
+            delete S;
+            return fail(FSKMC_EINVAL, "coarse cells of %dx%d blocks do not tile the %dx%d block grid", nest->cx,
+                        nest->cy, S->NBX, S->NBY);
+        }
+        if ((S->k_outer != 2 && S->k_outer != 4) || (S->k_inner != 2 && S->k_inner != 4)) {
+            delete S;
+            return fail(FSKMC_EINVAL, "outer and inner colourings have 2 or 4 colours");
+        }
+        S->NCX = S->NBX / S->cx;
+        S->NCY = S->NBY / S->cy;
+        auto builtin = [](int k, int i, int j) { return k == 2 ? (i + j) % 2 : (i % 2) + 2 * (j % 2); };
+        S->cell_off.assign(S->k_outer + 1, 0);
+        for (int c = 0; c < S->k_outer; ++c) {
+            S->cell_off[c] = (int32_t)S->cells.size();
+            for (int q = 0; q < S->NCX * S->NCY; ++q)
+                if (builtin(S->k_outer, q % S->NCX, q / S->NCX) == c)
+                    S->cells.push_back(q);
+        }
+        S->cell_off[S->k_outer] = (int32_t)S->cells.size();
+        S->cmap.resize(S->nb);
+        for (int m = 0; m < S->nb; ++m) {
+            const int bi = m % S->NBX, bj = m / S->NBX;
+            S->cmap[m] = builtin(S->k_outer, bi / S->cx, bj / S->cy) * S->k_inner +
+                         builtin(S->k_inner, bi % S->cx, bj % S->cy);
+        }
+        if ((rc = check_coarse(*S))) {
+            delete S;
+            return rc;
+        }
+        S->nest_kernel_ok = S->cx == S->cy && nested_supported(kernel_model(model), S->P, S->cx, S->k_inner);
+    }
     S->cmap.resize(S->nb);
-    for (int m = 0; m < S->nb; ++m) {
+    for (int m = 0; m < S->nb && !nest; ++m) {
         const int bi = m % S->NBX, bj = m / S->NBX;
         int c;
         if (decomp->colour_map) {
@@ -980,7 +1136,7 @@ int fskmc_sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, co
         S->max_per_colour = std::max(S->max_per_colour, (int)S->blocks.size() - S->colour_off[c]);
     }
     S->colour_off[S->n_colours] = (int32_t)S->blocks.size();
-    if ((rc = check_decomposition(*S)) || (rc = build_schedule(*S))) {
+    if ((rc = check_decomposition(*S)) || (rc = nest ? build_nested_schedule(*S) : build_schedule(*S))) {
         delete S;
         return rc;
     }
@@ -1016,7 +1172,7 @@ int fskmc_sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, co
         (rc = dev_alloc(&S->d_wdur, S->n_windows)) || (rc = dev_alloc(&S->d_bcol, S->nb)) ||
         (rc = dev_alloc(&S->d_next, S->next_part.size())) || (rc = dev_alloc(&S->d_nbr, nbr.size())) ||
         (rc = dev_alloc(&S->d_epoch, S->nb)) || (rc = dev_alloc(&S->d_prev, S->prev_part.size())) ||
-        (rc = dev_alloc(&S->d_edge, 4 * (size_t)S->nb))) {
+        (rc = dev_alloc(&S->d_edge, 4 * (size_t)S->nb)) || (rc = dev_alloc(&S->d_cells, S->cells.size()))) {
         free_sim_device(S);
         delete S;
         return rc;
@@ -1025,6 +1181,8 @@ int fskmc_sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, co
     hipError_t e = hipSuccess;
     if (e == hipSuccess)
         e = hipMemcpyAsync(S->d_bcol, bcol.data(), bcol.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !S->cells.empty())
+        e = hipMemcpyAsync(S->d_cells, S->cells.data(), S->cells.size() * 4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(S->d_next, S->next_part.data(), S->next_part.size() * 4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
@@ -1052,6 +1210,22 @@ int fskmc_sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, co
     }
     *out = S;
     return FSKMC_OK;
+}
+
+int fskmc_sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const void* params,
+                     const fskmc_decomp* decomp, const fskmc_schedule* schedule, fskmc_key key, fskmc_sim** out)
+{
+    return sim_create(ctx, lattice, model, params, decomp, schedule, key, nullptr, out);
+}
+
+int fskmc_sim_create_nested(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const void* params,
+                            const fskmc_nested* nested, const fskmc_schedule* schedule, fskmc_key key,
+                            fskmc_sim** out)
+{
+    if (!nested)
+        return fail(FSKMC_EINVAL, "NULL argument");
+    const fskmc_decomp d{nested->bx, nested->by, nested->outer_colours * nested->inner_colours, nullptr};
+    return sim_create(ctx, lattice, model, params, &d, schedule, key, nested, out);
 }
 
 int fskmc_sim_destroy(fskmc_sim* S)
@@ -1130,6 +1304,16 @@ int fskmc_sim_advance(fskmc_sim* S, uint64_t n_windows)
         return fail(FSKMC_EINVAL, "sim is NULL");
     if (n_windows > S->n_windows - S->window)
         return fail(FSKMC_ESTATE, "only %llu windows left before T", (unsigned long long)(S->n_windows - S->window));
+    if (S->nested && S->nest_kernel_ok && S->ctx->nested_kernel) {
+        const uint64_t end = S->window + n_windows;
+        while (S->window < end) {
+            const uint64_t w1 = std::min<uint64_t>(end, S->outer_end[S->window]);
+            if (int rc = enqueue_nested(S, S->window, w1))
+                return rc;
+            S->window = w1;
+        }
+        return FSKMC_OK;
+    }
     if (S->ctx->persist > 0) {
         uint64_t left = n_windows;
         while (left > 0) {

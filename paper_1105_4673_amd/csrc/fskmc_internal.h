@@ -95,6 +95,23 @@ struct ResidentArgs {
     unsigned long long wait_ticks;
 };
 
+// Nested sweep (Sec. 6, eqs. sublatt2 and opdecomp2): one workgroup per coarse
+// cell of the active outer colour; the cell's fine blocks (one wave each per
+// inner window) share one LDS tile and run the inner windows [w0, w1) of one
+// outer window separated by workgroup barriers.
+struct NestedArgs {
+    uint8_t* lat;
+    const double* table;
+    BlockCount* cnt;
+    const int8_t* win_colour; // flat colour = outer * k_inner + inner
+    const double* win_dur;
+    const int32_t* cells;     // coarse cells of the active outer colour, J * NCX + I
+    int n_cells;
+    int Lx, Ly, NBX, NCX;
+    uint32_t k0, k1;
+    int w0, w1;
+};
+
 // Optional kernel-side timing: when both events are set, the launch records
 // them at the kernel's own start and end (hipExtLaunchKernelGGL).
 struct LaunchTiming {
@@ -123,6 +140,11 @@ hipError_t launch_rebalance(const BlockCount* cnt, unsigned long long* ev_prev, 
                             const int8_t* win_colour, int pw0, int pw1, int first, unsigned long long base,
                             unsigned long long* scan, int32_t* owner, int nb, int use, int n_waves, int cap,
                             hipStream_t s);
+// Nested sweep variants: square coarse cells of c x c fine blocks of P*64
+// sites with k_inner inner colours; nested_supported() says which exist.
+bool nested_supported(int model, int P, int c, int k_inner);
+hipError_t launch_sweep_nested(int model, int P, int c, int k_inner, const NestedArgs& a, hipStream_t s,
+                               LaunchTiming tm);
 hipError_t launch_epoch_init(int32_t* epoch, const int8_t* bcol, const int32_t* next_part, int nb, int n_windows,
                              int w0, hipStream_t s);
 hipError_t launch_init(uint8_t* lat, int64_t n, int kind, double p, uint32_t k0, uint32_t k1,

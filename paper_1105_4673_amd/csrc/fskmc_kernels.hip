@@ -411,7 +411,7 @@ __device__ __forceinline__ void finish_tree(Tree<P>& T)
 // Leaves from the LDS tile: the table entry of each site's neighbourhood
 // (spin flip: s*(z+1) + #occupied neighbours; reaction model: the pattern
 // s + 3E + 9W + 27N + 81S).
-template <int P, int BX, int BY, int MODEL>
+template <int P, int BX, int BY, int MODEL, int TS = BX + 2 * P>
 __device__ __forceinline__ void build_tree(const uint8_t* tile, int tb, const double* tab, Tree<P>& T)
 {
     using C = Cfg<P, BX, BY, MODEL>;
@@ -419,8 +419,8 @@ __device__ __forceinline__ void build_tree(const uint8_t* tile, int tb, const do
     const uint32_t lft = tile[tb - 1], rgt = tile[tb + P];
     Seg<P> up, dn;
     if constexpr (C::DIM == 2) {
-        up = load_seg<P>(tile + tb + C::S); // +y
-        dn = load_seg<P>(tile + tb - C::S); // -y
+        up = load_seg<P>(tile + tb + TS); // +y
+        dn = load_seg<P>(tile + tb - TS); // -y
     }
 #pragma unroll
     for (int q = 0; q < P; ++q) {
@@ -450,10 +450,9 @@ struct FlipSites {
     uint32_t s[(P + 3) / 4], n[(P + 3) / 4];
 };
 
-template <int P, int BX, int BY>
+template <int P, int BX, int BY, int S = BX + 2 * P>
 __device__ __forceinline__ void flip_sites_from_tile(const uint8_t* tile, int tb, FlipSites<P>& F)
 {
-    constexpr int S = BX + 2 * P;
     constexpr int W = (P + 3) / 4;
     const Seg<P> o = load_seg<P>(tile + tb);
     const uint32_t lft = tile[tb - 1], rgt = tile[tb + P];
@@ -584,7 +583,10 @@ __device__ __forceinline__ int descend(const Tree<P>& T, double tg, int lane, do
 // into the tile at the end; pair events update the tile in place.
 // Returns the number of accepted events.  With `pre`, (nl0, v0) are this
 // lane's -log U and V of draw e = lane, computed by the caller ahead of time.
-template <int P, int BX, int BY, int MODEL>
+// TS: row stride of the tile (the block's own tile by default; a larger
+// shared tile when several waves hold the sub-blocks of one coarse cell, in
+// which case `tile` points at the sub-block's origin minus one row and P columns).
+template <int P, int BX, int BY, int MODEL, int TS = BX + 2 * P>
 __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const double* __restrict__ chan, uint32_t m,
                                                uint32_t w, double dur, uint32_t k0, uint32_t k1, bool pre = false,
                                                double nl0 = 0.0, double v0 = 0.0)
@@ -592,14 +594,14 @@ __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const
     using C = Cfg<P, BX, BY, MODEL>;
     const int lane = threadIdx.x & 63;
     const int r = lane / C::LPR, c0 = (lane % C::LPR) * P;
-    const int tb = (r + 1) * C::S + P + c0;
+    const int tb = (r + 1) * TS + P + c0;
     Tree<P> T;
     FlipSites<P> F;
     if constexpr (MODEL == MODEL_FLIP) {
-        flip_sites_from_tile<P, BX, BY>(tile, tb, F);
+        flip_sites_from_tile<P, BX, BY, TS>(tile, tb, F);
         flip_leaves<P, C::Z>(F, tab, T);
     } else {
-        build_tree<P, BX, BY, MODEL>(tile, tb, tab, T);
+        build_tree<P, BX, BY, MODEL, TS>(tile, tb, tab, T);
     }
 
     double t = 0.0;
@@ -639,9 +641,9 @@ __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const
             flip_apply<P, BX, BY>(F, lane, lx, ly, !was);
             flip_leaves<P, C::Z>(F, tab, T);
         } else {
-            const int ts = (ly + 1) * C::S + P + lx;
+            const int ts = (ly + 1) * TS + P + lx;
             const uint32_t s = tile[ts];
-            const uint32_t nE = tile[ts + 1], nW = tile[ts - 1], nN = tile[ts + C::S], nS = tile[ts - C::S];
+            const uint32_t nE = tile[ts + 1], nW = tile[ts - 1], nN = tile[ts + TS], nS = tile[ts - TS];
             const int pat = __builtin_amdgcn_readfirstlane((int)(s + 3 * nE + 9 * nW + 27 * nN + 81 * nS));
             const double* ch = chan + pat * 14;
             int pick = -1, last = -1;
@@ -663,7 +665,7 @@ __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const
                     tile[ts] = 1;
                 } else {
                     const int d = (pick - 1) & 3;
-                    const int off = d == 0 ? 1 : d == 1 ? -1 : d == 2 ? C::S : -C::S;
+                    const int off = d == 0 ? 1 : d == 1 ? -1 : d == 2 ? TS : -TS;
                     if (pick <= 4) {
                         tile[ts] = 2;
                         tile[ts + off] = 2;
@@ -677,7 +679,7 @@ __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const
                 }
             }
             wave_sync();
-            build_tree<P, BX, BY, MODEL>(tile, tb, tab, T);
+            build_tree<P, BX, BY, MODEL, TS>(tile, tb, tab, T);
         }
         ++e;
         if (e == 0xFFFFFFFFu)
@@ -1101,6 +1103,148 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
         const int m = m0 + i;
         const int x0 = (m % a.NBX) * BX, y0 = (m / a.NBX) * BY;
         store_seg<P>(a.lat + (size_t)(y0 + r) * sLx + x0 + c0, load_seg<P>(wl + i * C::TILE + tb));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Nested sweep (Sec. 6, eqs. sublatt2 and opdecomp2).  A coarse cell of C x C
+// fine blocks is one workgroup; its tile (cell plus the one-site ring of the
+// neighbouring cells, frozen for the outer window) is staged once into LDS.
+// In every inner window the blocks of the active inner colour run their SSA
+// windows concurrently, one wave each, on the shared tile: their neighbours in
+// other fine blocks are plain LDS reads, and the workgroup barrier between
+// inner windows is the only synchronisation.  At the end the cell (pair
+// models: cell and ring) goes back to HBM.  Draws use the global block id and
+// window index, so the result is the flat scheme's on the product colouring.
+template <int P, int B, int MODEL, int CC, int KI>
+struct NestCfg {
+    using C = Cfg<P, B, B, MODEL>;
+    static constexpr int WPG = CC * CC / KI;
+    static constexpr int CS = CC * B;                            // cell side in sites
+    static constexpr int TS = CS + 2 * P;                        // tile row stride
+    static constexpr int TILE = ((CS + 2) * TS + 15) / 16 * 16;
+    static constexpr int WAVE = (C::NTAB * 8 + C::XFER + 15) / 16 * 16; // per-wave table copy + exchange
+    static constexpr int LDS = TILE + WPG * WAVE;
+    static_assert(KI == 2 || KI == 4, "inner colourings: 2 (checkerboard) or 4");
+    static_assert(CC % 2 == 0 && WPG <= 16, "cells of an even number of blocks, at most 16 waves");
+};
+
+// Position (lx, ly) in the cell of the j-th fine block of inner colour ci,
+// for the inner colourings (lx+ly)%2 and (lx%2)+2(ly%2), row by row.
+template <int CC, int KI>
+__device__ __forceinline__ void nest_slot(int ci, int j, int& lx, int& ly)
+{
+    if constexpr (KI == 2) {
+        ly = j / (CC / 2);
+        lx = 2 * (j % (CC / 2)) + ((ly + ci) & 1);
+    } else {
+        ly = 2 * (j / (CC / 2)) + (ci >> 1);
+        lx = 2 * (j % (CC / 2)) + (ci & 1);
+    }
+}
+
+__device__ __forceinline__ int wrap(int v, int n)
+{
+    return v < 0 ? v + n : (v >= n ? v - n : v);
+}
+
+// Copy rows [r0, r1) (cell coordinates, -1 and CS are the ring) of the cell's
+// interior columns between HBM and the tile, words where the layout allows.
+template <int P, int TS, int CS, bool TO_LDS>
+__device__ __forceinline__ void nest_rows(uint8_t* tile, uint8_t* lat, int Lx, int Ly, int x0, int y0, int r0, int r1,
+                                          int tid, int nthr)
+{
+    if constexpr (P % 4 == 0) {
+        constexpr int WR = CS / 4;
+        for (int i = tid; i < (r1 - r0) * WR; i += nthr) {
+            const int y = r0 + i / WR, x = 4 * (i % WR);
+            uint32_t* g = reinterpret_cast<uint32_t*>(lat + (size_t)wrap(y0 + y, Ly) * Lx + x0 + x);
+            uint32_t* t = reinterpret_cast<uint32_t*>(tile + (y + 1) * TS + P + x);
+            if constexpr (TO_LDS)
+                *t = *g;
+            else
+                *g = *t;
+        }
+    } else {
+        for (int i = tid; i < (r1 - r0) * CS; i += nthr) {
+            const int y = r0 + i / CS, x = i % CS;
+            uint8_t* g = lat + (size_t)wrap(y0 + y, Ly) * Lx + x0 + x;
+            uint8_t* t = tile + (y + 1) * TS + P + x;
+            if constexpr (TO_LDS)
+                *t = *g;
+            else
+                *g = *t;
+        }
+    }
+}
+
+// The ring columns -1 and CS of rows [0, CS).
+template <int P, int TS, int CS, bool TO_LDS>
+__device__ __forceinline__ void nest_cols(uint8_t* tile, uint8_t* lat, int Lx, int Ly, int x0, int y0, int tid,
+                                          int nthr)
+{
+    for (int i = tid; i < 2 * CS; i += nthr) {
+        const int y = i >> 1, x = (i & 1) ? CS : -1;
+        uint8_t* g = lat + (size_t)wrap(y0 + y, Ly) * Lx + wrap(x0 + x, Lx);
+        uint8_t* t = tile + (y + 1) * TS + P + x;
+        if constexpr (TO_LDS)
+            *t = *g;
+        else
+            *g = *t;
+    }
+}
+
+template <int P, int B, int MODEL, int CC, int KI>
+__global__ __launch_bounds__(64 * (CC * CC / KI)) void k_sweep_nested(NestedArgs a)
+{
+    using N = NestCfg<P, B, MODEL, CC, KI>;
+    using C = Cfg<P, B, B, MODEL>;
+    constexpr int NT = 64 * N::WPG;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[N::LDS];
+    __shared__ int changed;
+    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    const int cell = a.cells[xcd_order(blockIdx.x, gridDim.x)];
+    const int I = cell % a.NCX, J = cell / a.NCX;
+    const int x0 = I * N::CS, y0 = J * N::CS;
+    uint8_t* tile = lds;
+    double* tab = reinterpret_cast<double*>(lds + N::TILE + wid * N::WAVE);
+    for (int i = lane; i < C::NTAB; i += 64)
+        tab[i] = (MODEL == MODEL_FLIP) ? a.table[i] : a.table[i * 14 + 13];
+    if (tid == 0)
+        changed = 0;
+    nest_rows<P, N::TS, N::CS, true>(tile, a.lat, a.Lx, a.Ly, x0, y0, -1, N::CS + 1, tid, NT);
+    nest_cols<P, N::TS, N::CS, true>(tile, a.lat, a.Lx, a.Ly, x0, y0, tid, NT);
+    __syncthreads();
+
+    uint32_t mine = 0;
+    for (int w = a.w0; w < a.w1; ++w) {
+        const int ci = (int)a.win_colour[w] % KI;
+        int lx, ly;
+        nest_slot<CC, KI>(ci, wid, lx, ly);
+        const int m = (J * CC + ly) * a.NBX + I * CC + lx;
+        uint8_t* sub = tile + ly * B * N::TS + lx * B;
+        const uint32_t e =
+            ssa_window<P, B, B, MODEL, N::TS>(sub, tab, a.table, (uint32_t)m, (uint32_t)w, a.win_dur[w], a.k0, a.k1);
+        if (lane == 0) {
+            a.cnt[m].W = e;
+            if (e > 0) {
+                atomicAdd(&a.cnt[m].writes, 1u);
+                atomicAdd(&a.cnt[m].events, (unsigned long long)e);
+            }
+        }
+        mine |= e;
+        __syncthreads();
+    }
+    if (lane == 0 && mine)
+        changed = 1;
+    __syncthreads();
+    if (!changed)
+        return;
+    if constexpr (MODEL == MODEL_FLIP) {
+        nest_rows<P, N::TS, N::CS, false>(tile, a.lat, a.Lx, a.Ly, x0, y0, 0, N::CS, tid, NT);
+    } else {
+        nest_rows<P, N::TS, N::CS, false>(tile, a.lat, a.Lx, a.Ly, x0, y0, -1, N::CS + 1, tid, NT);
+        nest_cols<P, N::TS, N::CS, false>(tile, a.lat, a.Lx, a.Ly, x0, y0, tid, NT);
     }
 }
 
@@ -1584,6 +1728,40 @@ hipError_t launch_sweep_persistent(int model, int P, int shape, int wpg, const P
         FSKMC_SW(MODEL_ZGB)
     }
 #undef FSKMC_SW
+}
+
+template <int MODEL, int CC, int KI>
+static hipError_t nested_p(int P, const NestedArgs& a, hipStream_t s, LaunchTiming tm)
+{
+    constexpr int T = 64 * (CC * CC / KI);
+    switch (P) {
+    case 1: return launch(k_sweep_nested<1, 8, MODEL, CC, KI>, dim3(a.n_cells), dim3(T), s, tm, a);
+    case 4: return launch(k_sweep_nested<4, 16, MODEL, CC, KI>, dim3(a.n_cells), dim3(T), s, tm, a);
+    case 16: return launch(k_sweep_nested<16, 32, MODEL, CC, KI>, dim3(a.n_cells), dim3(T), s, tm, a);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+bool nested_supported(int model, int P, int c, int k_inner)
+{
+    if (P != 1 && P != 4 && P != 16)
+        return false;
+    if (model == MODEL_FLIP)
+        return (c == 2 && k_inner == 2) || (c == 4 && (k_inner == 2 || k_inner == 4));
+    return k_inner == 4 && (c == 2 || c == 4);
+}
+
+hipError_t launch_sweep_nested(int model, int P, int c, int k_inner, const NestedArgs& a, hipStream_t s,
+                               LaunchTiming tm)
+{
+    if (!nested_supported(model, P, c, k_inner) || a.n_cells <= 0 || a.w1 <= a.w0)
+        return hipErrorInvalidValue;
+    if (model == MODEL_FLIP) {
+        if (c == 2)
+            return nested_p<MODEL_FLIP, 2, 2>(P, a, s, tm);
+        return k_inner == 2 ? nested_p<MODEL_FLIP, 4, 2>(P, a, s, tm) : nested_p<MODEL_FLIP, 4, 4>(P, a, s, tm);
+    }
+    return c == 2 ? nested_p<MODEL_ZGB, 2, 4>(P, a, s, tm) : nested_p<MODEL_ZGB, 4, 4>(P, a, s, tm);
 }
 
 static unsigned grid_for(int64_t n, int bs)

@@ -44,6 +44,12 @@ class fskmc_kawasaki_params(ctypes.Structure):
     _fields_ = [("D", ctypes.c_double), ("J", ctypes.c_double), ("beta", ctypes.c_double)]
 
 
+class fskmc_nested(ctypes.Structure):
+    _fields_ = [("bx", ctypes.c_int), ("by", ctypes.c_int), ("cx", ctypes.c_int), ("cy", ctypes.c_int),
+                ("outer_colours", ctypes.c_int), ("inner_colours", ctypes.c_int), ("inner_split", ctypes.c_int),
+                ("dtau", ctypes.c_double)]
+
+
 class fskmc_decomp(ctypes.Structure):
     _fields_ = [("bx", ctypes.c_int), ("by", ctypes.c_int), ("n_colours", ctypes.c_int),
                 ("colour_map", ctypes.POINTER(ctypes.c_int))]
@@ -72,7 +78,7 @@ SYMBOLS = [
     "fskmc_sim_footprint", "fskmc_batch_advance", "fskmc_sync", "fskmc_ctx_set_waves_per_group",
     "fskmc_ctx_set_kernel_timing", "fskmc_ctx_read_kernel_timing", "fskmc_ctx_set_persistent",
     "fskmc_ctx_set_resident", "fskmc_ctx_set_wait_limit", "fskmc_ctx_set_rebalance", "fskmc_sim_workload",
-    "fskmc_workload_partition", "fskmc_sim_last_partition",
+    "fskmc_workload_partition", "fskmc_sim_last_partition", "fskmc_sim_create_nested", "fskmc_ctx_set_nested",
 ]
 
 
@@ -99,6 +105,9 @@ def _load():
     L.fskmc_ctx_read_kernel_timing.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_uint64)]
     L.fskmc_sim_create.argtypes = [vp, P(fskmc_lattice), ctypes.c_int, vp, P(fskmc_decomp), P(fskmc_schedule),
                                    fskmc_key, P(vp)]
+    L.fskmc_sim_create_nested.argtypes = [vp, P(fskmc_lattice), ctypes.c_int, vp, P(fskmc_nested),
+                                          P(fskmc_schedule), fskmc_key, P(vp)]
+    L.fskmc_ctx_set_nested.argtypes = [vp, ctypes.c_int]
     L.fskmc_sim_destroy.argtypes = [vp]
     L.fskmc_sim_attach_device_lattice.argtypes = [vp, vp, ctypes.c_size_t]
     L.fskmc_sim_init.argtypes = [vp, ctypes.c_int, ctypes.c_double]
@@ -210,21 +219,41 @@ def _decomp(bx, by, n_colours, colour_map):
     return fskmc_decomp(bx, by, n_colours, cm), keep
 
 
+def _params(model, params):
+    if model == FSKMC_MODEL_FLIP:
+        return fskmc_flip_params(*params)
+    if model == FSKMC_MODEL_KAWASAKI:
+        return fskmc_kawasaki_params(*params)
+    return fskmc_zgb_params(*params)
+
+
 def fskmc_sim_create(ctx, dim, Lx, Ly, model, params, bx, by, n_colours, dt, T, split, seed, replica,
                      colour_map=None):
     lat = fskmc_lattice(dim, Lx, Ly)
-    if model == FSKMC_MODEL_FLIP:
-        p = fskmc_flip_params(*params)
-    elif model == FSKMC_MODEL_KAWASAKI:
-        p = fskmc_kawasaki_params(*params)
-    else:
-        p = fskmc_zgb_params(*params)
+    p = _params(model, params)
     dec, _keep = _decomp(bx, by, n_colours, colour_map)
     sch = fskmc_schedule(dt, T, split)
     out = ctypes.c_void_p()
     _check(lib.fskmc_sim_create(ctx, ctypes.byref(lat), model, ctypes.cast(ctypes.byref(p), ctypes.c_void_p),
                                 ctypes.byref(dec), ctypes.byref(sch), fskmc_key(seed, replica), ctypes.byref(out)))
     return out
+
+
+def fskmc_sim_create_nested(ctx, Lx, Ly, model, params, bx, by, cx, cy, outer_colours, inner_colours, inner_split,
+                            dtau, dt, T, split, seed, replica):
+    lat = fskmc_lattice(2, Lx, Ly)
+    p = _params(model, params)
+    nd = fskmc_nested(bx, by, cx, cy, outer_colours, inner_colours, inner_split, dtau)
+    sch = fskmc_schedule(dt, T, split)
+    out = ctypes.c_void_p()
+    _check(lib.fskmc_sim_create_nested(ctx, ctypes.byref(lat), model, ctypes.cast(ctypes.byref(p), ctypes.c_void_p),
+                                       ctypes.byref(nd), ctypes.byref(sch), fskmc_key(seed, replica),
+                                       ctypes.byref(out)))
+    return out
+
+
+def fskmc_ctx_set_nested(ctx, on):
+    _check(lib.fskmc_ctx_set_nested(ctx, 1 if on else 0))
 
 
 def fskmc_sim_destroy(sim):
@@ -313,11 +342,14 @@ class Sim:
     """One lattice simulation on the GPU.
 
     kind 'flip': params (k_a, k_d, J, h, beta); kind 'zgb': params (y, k_r, D);
-    kind 'kawasaki': params (D, J, beta).
+    kind 'kawasaki': params (D, J, beta).  nested: a dict with keys cx, cy,
+    outer_colours, inner_colours, inner_split and dtau for the nested
+    decomposition (fskmc_sim_create_nested); n_colours is then ignored.
     """
 
     def __init__(self, ctx, kind, Lx, Ly=1, params=(1.0, 1.0, 0.0, 0.0, 1.0), b=None, bx=None, by=None,
-                 n_colours=2, dt=0.1, T=1.0, split=FSKMC_LIE, seed=0, replica=0, colour_map=None, dim=None):
+                 n_colours=2, dt=0.1, T=1.0, split=FSKMC_LIE, seed=0, replica=0, colour_map=None, dim=None,
+                 nested=None):
         self.ctx = ctx
         self.kind = kind
         self.dim = dim if dim is not None else (1 if Ly == 1 else 2)
@@ -329,8 +361,15 @@ class Sim:
         if kind not in MODELS:
             raise ValueError(f"unknown model kind {kind!r}")
         self.model = MODELS[kind]
-        self.handle = fskmc_sim_create(ctx, self.dim, Lx, Ly, self.model, params, bx, by, n_colours, dt, T, split,
-                                       seed, replica, colour_map)
+        if nested is not None:
+            n = dict(nested)
+            self.n_colours = n["outer_colours"] * n["inner_colours"]
+            self.handle = fskmc_sim_create_nested(ctx, Lx, Ly, self.model, params, bx, by, n["cx"], n["cy"],
+                                                  n["outer_colours"], n["inner_colours"], n["inner_split"],
+                                                  n["dtau"], dt, T, split, seed, replica)
+        else:
+            self.handle = fskmc_sim_create(ctx, self.dim, Lx, Ly, self.model, params, bx, by, n_colours, dt, T,
+                                           split, seed, replica, colour_map)
         self.N = Lx * Ly
         self.nb = (Lx // bx) * (Ly // by)
 

@@ -19,6 +19,15 @@ def c1(J=1.0, dt=0.1, split=0, T=100.0):
                 params=(1.0, 1.0, J, 0.0, 1.0), b=16, n_colours=2, dt=dt, T=T, split=split, init="bernoulli")
 
 
+def nested(c=4, dtau=0.05, T=20.0, dt=0.1, J=1.0):
+    """The 1024^2 spin-flip lattice on a nested decomposition: coarse cells of
+    c x c blocks of 16x16, 2 outer x 2 inner colours, outer Lie dt, inner Lie
+    dtau, from Bernoulli(1/2)."""
+    return dict(name=f"ising1024_b16_J{J:g}_nested_c{c}_lie{dt:g}_lie{dtau:g}_T{T:g}", kind="flip", Lx=1024,
+                Ly=1024, params=(1.0, 1.0, J, 0.0, 1.0), b=16, dt=dt, T=T, split=0, init="bernoulli",
+                nested=dict(cx=c, cy=c, outer_colours=2, inner_colours=2, inner_split=0, dtau=dtau))
+
+
 def c2(y=0.5, D=10.0, T=10.0, L=4096):
     """4096^2 A/B reaction lattice, 32x32 blocks, 4 colours, Strang dt=0.05,
     empty start, k_r = 1e3."""
