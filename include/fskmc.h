@@ -231,11 +231,32 @@ int fskmc_sim_set_state(fskmc_sim* sim, uint64_t window, const uint8_t* host, si
 size_t fskmc_sim_footprint(const fskmc_lattice* lattice, int model, const fskmc_decomp* decomp,
                            const fskmc_schedule* schedule);
 
-/* Advance n simulations (same context) by up to `windows` windows each in
- * one launch per window: every launch runs the current window of every sim
- * that still has windows left, all blocks of all sims packed into one grid.
- * Each sim's result is bit-identical to advancing it alone. */
+/* Advance n simulations (same context) by up to `windows` windows each.
+ * By default one launch per window: every launch runs the current window of
+ * every sim that still has windows left, all blocks of all sims packed into
+ * one grid.  With fskmc_ctx_set_batch_persistent(ctx, K > 0), K windows of
+ * every sim run in one persistent launch whose waves take (window, job,
+ * block) work items from a device counter in window order, each block
+ * waiting only for the blocks it interacts with (Sec. 2.2 stage 2).  Sims
+ * are grouped by kernel variant (model family, block shape); each group is
+ * launched on its own.  The launch sequence is captured as a HIP graph and
+ * replayed by later calls with the same layout (fskmc_ctx_set_graphs).
+ * Each sim's result is bit-identical to advancing it alone.  FSKMC_EDEVICE
+ * at the next synchronising call if a persistent wait timed out (the lattices
+ * of that batch are then unspecified). */
 int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t windows);
+
+/* Knob that never changes results (default 0): windows per persistent
+ * launch of fskmc_batch_advance; 0 = one packed launch per window. */
+int fskmc_ctx_set_batch_persistent(fskmc_ctx* ctx, int windows);
+
+/* Knob that never changes results (default on): fskmc_batch_advance records
+ * its launch sequence as a HIP graph once and replays it while the layout
+ * stays the same (the same sims in the same order, window count per call and
+ * knobs); the per-call job table is uploaded before each replay.  Off, and
+ * while kernel timing is on, the launches go to the stream directly.  The
+ * graph holds kernels only (counters and flags are cleared by kernels). */
+int fskmc_ctx_set_graphs(fskmc_ctx* ctx, int on);
 
 /* Wait for all work enqueued on the context's stream. */
 int fskmc_sync(fskmc_ctx* ctx);

@@ -92,6 +92,14 @@ struct fskmc_ctx {
     unsigned long long wait_ticks = 200000000ull; // longest neighbour wait: 2 s of the 100 MHz wall clock
     int32_t* d_abort = nullptr;  // raised by the persistent kernel on a timed-out wait
     int32_t* h_abort = nullptr;  // pinned copy, refreshed after each persistent launch
+    // batched advances: windows per persistent launch (0 = one packed launch
+    // per window), HIP graph replay of the launch sequence, the work counter
+    // of the persistent launches, and the cached graph with its layout key
+    uint32_t batch_persist = 0;
+    bool graphs = true;
+    unsigned long long* d_queue = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<uint64_t> graph_key;
 };
 
 struct fskmc_sim {
@@ -818,6 +826,7 @@ int fskmc_ctx_create(int device, void* hip_stream, fskmc_ctx** out)
         hipHostMalloc((void**)&c->h_obs, 16 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->stage_free, hipEventDisableTiming) != hipSuccess ||
         hipMalloc((void**)&c->d_abort, sizeof(int32_t)) != hipSuccess ||
+        hipMalloc((void**)&c->d_queue, sizeof(unsigned long long)) != hipSuccess ||
         hipHostMalloc((void**)&c->h_abort, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
         fskmc_ctx_destroy(c);
         return fail(FSKMC_ENOMEM, "context allocation failed");
@@ -838,6 +847,9 @@ int fskmc_ctx_destroy(fskmc_ctx* c)
     (void)hipHostFree(c->h_obs);
     (void)hipFree(c->d_abort);
     (void)hipHostFree(c->h_abort);
+    (void)hipFree(c->d_queue);
+    if (c->graph_exec)
+        (void)hipGraphExecDestroy(c->graph_exec);
     (void)hipFree(c->d_jobs);
     (void)hipFree(c->d_items);
     (void)hipHostFree(c->h_stage);
@@ -848,6 +860,24 @@ int fskmc_ctx_destroy(fskmc_ctx* c)
     if (c->own_stream && c->stream)
         (void)hipStreamDestroy(c->stream);
     delete c;
+    return FSKMC_OK;
+}
+
+int fskmc_ctx_set_batch_persistent(fskmc_ctx* c, int windows)
+{
+    if (!c)
+        return fail(FSKMC_EINVAL, "ctx is NULL");
+    if (windows < 0)
+        return fail(FSKMC_EINVAL, "windows must be >= 0");
+    c->batch_persist = (uint32_t)windows;
+    return FSKMC_OK;
+}
+
+int fskmc_ctx_set_graphs(fskmc_ctx* c, int on)
+{
+    if (!c)
+        return fail(FSKMC_EINVAL, "ctx is NULL");
+    c->graphs = on != 0;
     return FSKMC_OK;
 }
 
@@ -1550,6 +1580,12 @@ int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t 
             d.item_begin = item;
             d.n_items = (uint32_t)S->max_per_colour;
             d.pad = 0;
+            d.bcol = S->d_bcol;
+            d.next_part = S->d_next;
+            d.nbr = S->d_nbr;
+            d.epoch = S->d_epoch;
+            d.nb = S->nb;
+            d.pad2 = 0;
             for (int q = 0; q < S->max_per_colour; ++q)
                 hi[g.item_off + item + q] = (uint32_t)k;
             item += (uint32_t)S->max_per_colour;
@@ -1558,14 +1594,93 @@ int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t 
     HIP_TRY(hipMemcpyAsync(ctx->d_jobs, hj, n_jobs * sizeof(JobDesc), hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(hipMemcpyAsync(ctx->d_items, hi, n_items * 4, hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(hipEventRecord(ctx->stage_free, ctx->stream));
-    for (uint32_t step = 0; step < windows; ++step) {
-        for (auto& g : groups) {
-            const LaunchTiming tk = timing_begin(ctx);
-            HIP_TRY(launch_sweep_batched(g.model, g.P, g.shape, ctx->wpg, ctx->d_jobs + g.job_off,
-                                         ctx->d_items + g.item_off, g.items, step, ctx->stream, tk));
-            timing_end(ctx, tk);
+    const uint32_t K = ctx->batch_persist;
+    hipStream_t st = ctx->stream;
+    // The launch sequence of this call: one packed launch per window and
+    // group, or (K > 0) the epochs of every job, then per K windows and group
+    // a cleared work counter and one persistent launch.  It reads the job
+    // table through device pointers only, so a captured graph of it replays
+    // for any later call with the same layout.
+    auto enqueue = [&]() -> hipError_t {
+        hipError_t e = hipSuccess;
+        if (K == 0) {
+            for (uint32_t step = 0; step < windows && e == hipSuccess; ++step)
+                for (auto& g : groups) {
+                    const LaunchTiming tk = timing_begin(ctx);
+                    e = launch_sweep_batched(g.model, g.P, g.shape, ctx->wpg, ctx->d_jobs + g.job_off,
+                                             ctx->d_items + g.item_off, g.items, step, st, tk);
+                    timing_end(ctx, tk);
+                    if (e != hipSuccess)
+                        break;
+                }
+            return e;
         }
+        e = launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->d_abort), 1, 0u, st);
+        if (e == hipSuccess)
+            e = launch_epoch_init_batched(ctx->d_jobs, (int)n_jobs, st);
+        for (uint32_t s0 = 0; s0 < windows && e == hipSuccess; s0 += K) {
+            const uint32_t s1 = std::min<uint32_t>(windows, s0 + K);
+            for (auto& g : groups) {
+                const unsigned grid = batched_persistent_grid(g.P, g.shape, ctx->wpg);
+                const uint64_t total = (uint64_t)(s1 - s0) * g.items;
+                const uint64_t per = total / ((uint64_t)grid * ctx->wpg * 8);
+                BatchPersistArgs a{};
+                a.jobs = ctx->d_jobs + g.job_off;
+                a.item_job = ctx->d_items + g.item_off;
+                a.n_items = g.items;
+                a.s0 = s0;
+                a.s1 = s1;
+                a.chunk = (uint32_t)std::min<uint64_t>(16, std::max<uint64_t>(1, per));
+                a.queue = ctx->d_queue;
+                a.abort_flag = ctx->d_abort;
+                a.wait_ticks = ctx->wait_ticks;
+                e = launch_fill_u64(reinterpret_cast<uint64_t*>(ctx->d_queue), 1, 0ull, st);
+                if (e != hipSuccess)
+                    break;
+                const LaunchTiming tk = timing_begin(ctx);
+                e = launch_sweep_batched_persistent(g.model, g.P, g.shape, ctx->wpg, a, grid, st, tk);
+                timing_end(ctx, tk);
+                if (e != hipSuccess)
+                    break;
+            }
+        }
+        return e;
+    };
+    if (ctx->graphs && ctx->timing_stride == 0) {
+        std::vector<uint64_t> key = {windows, K, (uint64_t)ctx->wpg, (uint64_t)(uintptr_t)ctx->d_jobs,
+                                     (uint64_t)(uintptr_t)ctx->d_items, (uint64_t)(uintptr_t)st, n_jobs};
+        for (auto& g : groups)
+            key.insert(key.end(), {(uint64_t)g.model, (uint64_t)g.P, (uint64_t)g.shape, g.job_off, g.item_off,
+                                   g.items, g.idx.size()});
+        if (!ctx->graph_exec || key != ctx->graph_key) {
+            if (ctx->graph_exec) {
+                (void)hipGraphExecDestroy(ctx->graph_exec);
+                ctx->graph_exec = nullptr;
+            }
+            HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            const hipError_t e = enqueue();
+            hipGraph_t graph = nullptr;
+            const hipError_t ee = hipStreamEndCapture(st, &graph);
+            if (e != hipSuccess || ee != hipSuccess) {
+                if (graph)
+                    (void)hipGraphDestroy(graph);
+                return fail(FSKMC_EDEVICE, "graph capture of the batched launches failed: %s",
+                            hipGetErrorString(e != hipSuccess ? e : ee));
+            }
+            const hipError_t ie = hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) {
+                ctx->graph_exec = nullptr;
+                return fail(FSKMC_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+            }
+            ctx->graph_key = key;
+        }
+        HIP_TRY(hipGraphLaunch(ctx->graph_exec, st));
+    } else {
+        HIP_TRY(enqueue());
     }
+    if (K > 0)
+        HIP_TRY(hipMemcpyAsync(ctx->h_abort, ctx->d_abort, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     for (int i = 0; i < n; ++i) {
         fskmc_sim* S = sims[i];
         const uint64_t end = std::min<uint64_t>(S->n_windows, S->window + windows);

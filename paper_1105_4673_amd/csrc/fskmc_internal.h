@@ -49,6 +49,29 @@ struct JobDesc {
     uint32_t item_begin;        // first item of this job in the packed grid
     uint32_t n_items;           // items reserved (max blocks over colours)
     uint32_t pad;
+    // persistent batched sweep: colour per block, next window per colour
+    // ([n_colours][n_windows+1]), interacting blocks ([nb][8]), epochs
+    const int8_t* bcol;
+    const int32_t* next_part;
+    const int32_t* nbr;
+    int32_t* epoch;
+    int nb;
+    int pad2;
+};
+
+// Persistent batched sweep: batch steps [s0, s1) of every job in one launch.
+// Items (step, packed item) are taken in step-major order from a 64-bit
+// counter, `chunk` at a time; an item of window w waits until every block it
+// interacts with has finished its windows before w (per-job epochs).
+struct BatchPersistArgs {
+    const JobDesc* jobs;
+    const uint32_t* item_job;
+    uint32_t n_items;           // packed items per step
+    uint32_t s0, s1;
+    uint32_t chunk;
+    unsigned long long* queue;  // zero at launch
+    int32_t* abort_flag;
+    unsigned long long wait_ticks;
 };
 
 // Kernel arguments of the persistent multi-window sweep of one simulation.
@@ -140,6 +163,11 @@ hipError_t launch_rebalance(const BlockCount* cnt, unsigned long long* ev_prev, 
                             const int8_t* win_colour, int pw0, int pw1, int first, unsigned long long base,
                             unsigned long long* scan, int32_t* owner, int nb, int use, int n_waves, int cap,
                             hipStream_t s);
+hipError_t launch_sweep_batched_persistent(int model, int P, int shape, int wpg, const BatchPersistArgs& a,
+                                           unsigned grid, hipStream_t s, LaunchTiming tm);
+// Workgroups of one batched persistent launch that fill the device.
+unsigned batched_persistent_grid(int P, int shape, int wpg);
+hipError_t launch_epoch_init_batched(const JobDesc* jobs, int n_jobs, hipStream_t s);
 // Nested sweep variants: square coarse cells of c x c fine blocks of P*64
 // sites with k_inner inner colours; nested_supported() says which exist.
 bool nested_supported(int model, int P, int c, int k_inner);

@@ -822,6 +822,34 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_batched(const JobDesc* __res
                                    jd.k1, (uint32_t)w, jd.win_dur[w], lds + wid * C::LDS);
 }
 
+// Lanes 0..7 wait until each block that can interact with block m has
+// finished its windows before w (epoch >= w), bounded by wait_ticks of the
+// 100 MHz wall clock (then the abort flag is raised).  With `own`, lane 8
+// also waits for block m's own earlier windows: needed when windows of one
+// block may be taken by different waves, since two consecutive windows of
+// one colour have no neighbour window between them.  True when the launch is
+// aborting: every wave then leaves.
+__device__ __forceinline__ bool wait_neighbours(const int32_t* nbr, const int32_t* epoch, int m, int w, int lane,
+                                                int32_t* abort_flag, unsigned long long wait_ticks, bool own = false)
+{
+    if (lane < 8 || (own && lane == 8)) {
+        const int nb = lane == 8 ? m : nbr[m * 8 + lane];
+        if (nb >= 0) {
+            const uint64_t t0 = wall_clock64();
+            while (__hip_atomic_load(&epoch[nb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < w) {
+                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                    break;
+                if (wall_clock64() - t0 > wait_ticks) {
+                    __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+    }
+    return __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
 // Persistent multi-window sweep of one simulation (cooperative launch: every
 // wave is resident).  Windows [w0, w1) run in order inside the kernel and the
 // colour barrier becomes a neighbour-only wait, the local synchronisation of
@@ -848,22 +876,7 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_persistent(PersistArgs a)
         const int nxt = a.next_part[c * (a.n_windows + 1) + w + 1];
         for (int k = gw; k < count; k += a.n_waves) {
             const int m = a.blocks[beg + k];
-            if (lane < 8) {
-                const int nb = a.nbr[m * 8 + lane];
-                if (nb >= 0) {
-                    const uint64_t t0 = wall_clock64();
-                    while (__hip_atomic_load(&a.epoch[nb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < w) {
-                        if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                            break;
-                        if (wall_clock64() - t0 > a.wait_ticks) {
-                            __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
-                    }
-                }
-            }
-            if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            if (wait_neighbours(a.nbr, a.epoch, m, w, lane, a.abort_flag, a.wait_ticks))
                 return;
             // the lattice is read and written with agent-coherent accesses, so
             // only their order matters here: loads after the epoch loads,
@@ -881,6 +894,67 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_persistent(PersistArgs a)
                 __hip_atomic_store(&a.epoch[m], nxt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
+}
+
+// Persistent batched sweep: many windows of many simulations in one launch.
+// The work is the list of (step, packed item) pairs in step-major order; a
+// wave takes `chunk` consecutive pairs from a 64-bit counter and runs them in
+// order, with the per-job neighbour waits of the single-simulation persistent
+// sweep (its epochs, coherent accesses and completion wait), plus a wait for
+// the block's own previous window, which another wave may hold.  An item only
+// waits for items earlier in the list, which were taken by running waves that
+// run their own items in order, so the earliest unfinished item can always
+// proceed: no co-residency of the grid is needed.
+template <int P, int BX, int BY, int MODEL, int WPG>
+__global__ __launch_bounds__(64 * WPG) void k_sweep_batched_persistent(BatchPersistArgs a)
+{
+    using C = Cfg<P, BX, BY, MODEL>;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[WPG * C::LDS];
+    const int wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const uint64_t total = (uint64_t)(a.s1 - a.s0) * a.n_items;
+    for (;;) {
+        unsigned long long q0 = 0;
+        if (lane == 0)
+            q0 = atomicAdd(a.queue, (unsigned long long)a.chunk);
+        q0 = __shfl(q0, 0, 64);
+        if (q0 >= total)
+            return;
+        const uint64_t q1 = q0 + a.chunk < total ? q0 + a.chunk : total;
+        for (uint64_t q = q0; q < q1; ++q) {
+            const uint32_t s = a.s0 + (uint32_t)(q / a.n_items);
+            const uint32_t it = (uint32_t)(q % a.n_items);
+            const JobDesc& jd = a.jobs[a.item_job[it]];
+            const uint64_t w = jd.base_window + s;
+            if (w >= jd.n_windows)
+                continue;
+            const int c = jd.win_colour[w];
+            const uint32_t k = it - jd.item_begin;
+            const int beg = jd.colour_off[c], count = jd.colour_off[c + 1] - beg;
+            if (k >= (uint32_t)count)
+                continue;
+            const int m = jd.blocks[beg + k];
+            if (wait_neighbours(jd.nbr, jd.epoch, m, (int)w, lane, a.abort_flag, a.wait_ticks, true))
+                return;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            block_window<P, BX, BY, MODEL, true>(jd.lat, jd.table, jd.cnt, jd.Lx, jd.Ly, m, jd.NBX, jd.k0, jd.k1,
+                                                 (uint32_t)w, jd.win_dur[w], lds + wid * C::LDS);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_s_waitcnt(0x0F70); // lattice stores performed before the epoch
+            if (lane == 0) {
+                const int nxt = jd.next_part[(size_t)c * (jd.n_windows + 1) + w + 1];
+                __hip_atomic_store(&jd.epoch[m], nxt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+}
+
+// Epochs of every job of a batch at its current window: one workgroup per job.
+__global__ void k_epoch_init_batched(const JobDesc* __restrict__ jobs)
+{
+    const JobDesc& jd = jobs[blockIdx.x];
+    for (int m = threadIdx.x; m < jd.nb; m += blockDim.x)
+        jd.epoch[m] = jd.next_part[(size_t)jd.bcol[m] * (jd.n_windows + 1) + jd.base_window];
 }
 
 // ---------------------------------------------------------------------------
@@ -1396,10 +1470,16 @@ __global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v)
 // (+x and, in 2D, +y) with both ends k; the A-B bonds; and the sums of the
 // per-block event and write-back counters.  Each thread takes four
 // consecutive sites.
-__global__ void k_observe(const uint8_t* __restrict__ lat, int Lx, int Ly, int dim,
-                          const BlockCount* __restrict__ cnt, int n_blocks, unsigned long long* out)
+__global__ __launch_bounds__(256) void k_observe(const uint8_t* __restrict__ lat, int Lx, int Ly, int dim,
+                                                 const BlockCount* __restrict__ cnt, int n_blocks,
+                                                 unsigned long long* out)
 {
-    unsigned long long acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    // per-thread counts fit 32 bits (at most 4 sites and 8 bonds per item,
+    // at most 2^31 / 4 / (grid threads) items per thread); the wave and
+    // workgroup sums are 64-bit, one global atomic per workgroup and counter
+    __shared__ unsigned long long part[4][9];
+    uint32_t acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    unsigned long long ev = 0, wr = 0;
     const int64_t nq = (int64_t)Lx * Ly / 4;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nq; i += stride) {
@@ -1414,27 +1494,41 @@ __global__ void k_observe(const uint8_t* __restrict__ lat, int Lx, int Ly, int d
         for (int q = 0; q < 4; ++q) {
             const uint32_t s = (own >> (8 * q)) & 0xffu;
             const uint32_t rx = q < 3 ? (own >> (8 * (q + 1))) & 0xffu : nxt;
-            acc[s] += 1;
-            acc[3 + s] += (rx == s);
-            acc[6] += ((s == 1 && rx == 2) || (s == 2 && rx == 1));
+            acc[0] += s == 0;
+            acc[1] += s == 1;
+            acc[2] += s == 2;
+            acc[3] += s == 0 && rx == 0;
+            acc[4] += s == 1 && rx == 1;
+            acc[5] += s == 2 && rx == 2;
+            acc[6] += (s == 1 && rx == 2) || (s == 2 && rx == 1);
             if (dim == 2) {
                 const uint32_t ry = (up >> (8 * q)) & 0xffu;
-                acc[3 + s] += (ry == s);
-                acc[6] += ((s == 1 && ry == 2) || (s == 2 && ry == 1));
+                acc[3] += s == 0 && ry == 0;
+                acc[4] += s == 1 && ry == 1;
+                acc[5] += s == 2 && ry == 2;
+                acc[6] += (s == 1 && ry == 2) || (s == 2 && ry == 1);
             }
         }
     }
     for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < n_blocks; b += stride) {
-        acc[7] += cnt[b].events;
-        acc[8] += cnt[b].writes;
+        ev += cnt[b].events;
+        wr += cnt[b].writes;
     }
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
-        unsigned long long v = acc[c];
+        unsigned long long v = c < 7 ? (unsigned long long)acc[c] : (c == 7 ? ev : wr);
         for (int o = 32; o >= 1; o >>= 1)
             v += __shfl_xor(v, o, 64);
-        if ((threadIdx.x & 63) == 0 && v)
-            atomicAdd(out + c, v);
+        if (lane == 0)
+            part[wid][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        const unsigned long long v = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] +
+                                     part[3][threadIdx.x];
+        if (v)
+            atomicAdd(out + threadIdx.x, v);
     }
 }
 
@@ -1544,6 +1638,66 @@ hipError_t launch_sweep_batched(int model, int P, int shape, int wpg, const JobD
         FSKMC_SW(MODEL_ZGB)
     }
 #undef FSKMC_SW
+}
+
+template <int MODEL, int WPG>
+static hipError_t batched_persistent_dispatch(int P, int shape, const BatchPersistArgs& a, unsigned grid,
+                                              hipStream_t s, LaunchTiming tm)
+{
+    const dim3 g(grid), b(64 * WPG);
+    if (shape == SHAPE_SQ) {
+        switch (P) {
+        case 1: return launch(k_sweep_batched_persistent<1, 8, 8, MODEL, WPG>, g, b, s, tm, a);
+        case 4: return launch(k_sweep_batched_persistent<4, 16, 16, MODEL, WPG>, g, b, s, tm, a);
+        case 16: return launch(k_sweep_batched_persistent<16, 32, 32, MODEL, WPG>, g, b, s, tm, a);
+        }
+    } else if constexpr (MODEL == MODEL_FLIP) {
+        switch (P) {
+        case 1: return launch(k_sweep_batched_persistent<1, 64, 1, MODEL, WPG>, g, b, s, tm, a);
+        case 4: return launch(k_sweep_batched_persistent<4, 256, 1, MODEL, WPG>, g, b, s, tm, a);
+        case 16: return launch(k_sweep_batched_persistent<16, 1024, 1, MODEL, WPG>, g, b, s, tm, a);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep_batched_persistent(int model, int P, int shape, int wpg, const BatchPersistArgs& a,
+                                           unsigned grid, hipStream_t s, LaunchTiming tm)
+{
+    if (grid == 0 || a.chunk == 0 || a.s1 <= a.s0)
+        return hipErrorInvalidValue;
+    if (model == MODEL_FLIP) {
+        switch (wpg) {
+        case 1: return batched_persistent_dispatch<MODEL_FLIP, 1>(P, shape, a, grid, s, tm);
+        case 2: return batched_persistent_dispatch<MODEL_FLIP, 2>(P, shape, a, grid, s, tm);
+        case 4: return batched_persistent_dispatch<MODEL_FLIP, 4>(P, shape, a, grid, s, tm);
+        case 8: return batched_persistent_dispatch<MODEL_FLIP, 8>(P, shape, a, grid, s, tm);
+        }
+    } else {
+        switch (wpg) {
+        case 1: return batched_persistent_dispatch<MODEL_ZGB, 1>(P, shape, a, grid, s, tm);
+        case 2: return batched_persistent_dispatch<MODEL_ZGB, 2>(P, shape, a, grid, s, tm);
+        case 4: return batched_persistent_dispatch<MODEL_ZGB, 4>(P, shape, a, grid, s, tm);
+        case 8: return batched_persistent_dispatch<MODEL_ZGB, 8>(P, shape, a, grid, s, tm);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+unsigned batched_persistent_grid(int P, int shape, int wpg)
+{
+    (void)P;
+    (void)shape;
+    // 256 CUs x 8 waves; the queue balances the rest
+    return (unsigned)std::max(1, 2048 / std::max(wpg, 1));
+}
+
+hipError_t launch_epoch_init_batched(const JobDesc* jobs, int n_jobs, hipStream_t s)
+{
+    if (n_jobs <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_epoch_init_batched, dim3(n_jobs), dim3(256), 0, s, jobs);
+    return hipGetLastError();
 }
 
 // Cooperative launch of the persistent sweep: as many workgroups as can be
@@ -1809,8 +1963,8 @@ hipError_t launch_observe(const uint8_t* lat, int Lx, int Ly, int dim, const Blo
 {
     const int64_t work = std::max<int64_t>((int64_t)Lx * Ly / 4, n_blocks);
     unsigned g = grid_for(work, 256);
-    if (g > 2048)
-        g = 2048;
+    if (g > 256)
+        g = 256; // one workgroup per CU: 256 x 9 atomics per call
     hipLaunchKernelGGL(k_observe, dim3(g), dim3(256), 0, s, lat, Lx, Ly, dim, cnt, n_blocks, out9);
     return hipGetLastError();
 }

@@ -79,6 +79,7 @@ SYMBOLS = [
     "fskmc_ctx_set_kernel_timing", "fskmc_ctx_read_kernel_timing", "fskmc_ctx_set_persistent",
     "fskmc_ctx_set_resident", "fskmc_ctx_set_wait_limit", "fskmc_ctx_set_rebalance", "fskmc_sim_workload",
     "fskmc_workload_partition", "fskmc_sim_last_partition", "fskmc_sim_create_nested", "fskmc_ctx_set_nested",
+    "fskmc_ctx_set_batch_persistent", "fskmc_ctx_set_graphs",
 ]
 
 
@@ -108,6 +109,8 @@ def _load():
     L.fskmc_sim_create_nested.argtypes = [vp, P(fskmc_lattice), ctypes.c_int, vp, P(fskmc_nested),
                                           P(fskmc_schedule), fskmc_key, P(vp)]
     L.fskmc_ctx_set_nested.argtypes = [vp, ctypes.c_int]
+    L.fskmc_ctx_set_batch_persistent.argtypes = [vp, ctypes.c_int]
+    L.fskmc_ctx_set_graphs.argtypes = [vp, ctypes.c_int]
     L.fskmc_sim_destroy.argtypes = [vp]
     L.fskmc_sim_attach_device_lattice.argtypes = [vp, vp, ctypes.c_size_t]
     L.fskmc_sim_init.argtypes = [vp, ctypes.c_int, ctypes.c_double]
@@ -254,6 +257,14 @@ def fskmc_sim_create_nested(ctx, Lx, Ly, model, params, bx, by, cx, cy, outer_co
 
 def fskmc_ctx_set_nested(ctx, on):
     _check(lib.fskmc_ctx_set_nested(ctx, 1 if on else 0))
+
+
+def fskmc_ctx_set_batch_persistent(ctx, windows):
+    _check(lib.fskmc_ctx_set_batch_persistent(ctx, int(windows)))
+
+
+def fskmc_ctx_set_graphs(ctx, on):
+    _check(lib.fskmc_ctx_set_graphs(ctx, 1 if on else 0))
 
 
 def fskmc_sim_destroy(sim):

@@ -1,0 +1,135 @@
+"""Batched advances (needs a GPU): the persistent batched sweep (K windows of
+every sim per launch, work items from a device counter) and HIP-graph replay
+of the batch's launch sequence give every sim the bits it gets alone."""
+import hashlib
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+FLIP, ZGB, KAW = "flip", "zgb", "kawasaki"
+
+SPECS = [
+    dict(kind=FLIP, Lx=128, Ly=128, params=(1.0, 1.0, 1.5, -0.5, 1.0), b=16, n_colours=2, dt=0.1, T=2.0, split=0,
+         seed=0, replica=1),
+    dict(kind=FLIP, Lx=256, Ly=256, params=(1.0, 1.0, 0.3, 0.8, 1.0), b=16, n_colours=2, dt=0.2, T=2.0, split=1,
+         seed=0, replica=2),
+    dict(kind=FLIP, Lx=64, Ly=64, params=(1.0, 1.0, 1.0, 0.0, 1.0), b=8, n_colours=2, dt=0.1, T=3.0, split=2,
+         seed=0, replica=3),
+    dict(kind=ZGB, Lx=128, Ly=128, params=(0.5, 1000.0, 10.0), b=32, n_colours=4, dt=0.05, T=1.0, split=1, seed=0,
+         replica=4),
+    dict(kind=FLIP, Lx=512, Ly=1, params=(1.0, 1.0, 1.0, 0.0, 1.0), b=64, n_colours=2, dt=1.0, T=5.0, split=0,
+         seed=0, replica=5),
+    dict(kind=KAW, Lx=128, Ly=128, params=(4.0, 1.0, 1.0), b=16, n_colours=4, dt=0.25, T=3.0, split=1, seed=0,
+         replica=6),
+    dict(kind=FLIP, Lx=1024, Ly=1024, params=(1.0, 1.0, 1.0, 0.0, 1.0), b=16, n_colours=2, dt=0.1, T=1.0, split=0,
+         seed=0, replica=7),
+]
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_1105_4673_amd import fskmc
+    return fskmc
+
+
+@pytest.fixture()
+def ctx(F):
+    c = F.fskmc_ctx_create(0)
+    yield c
+    F.fskmc_ctx_destroy(c)
+
+
+def _make(F, ctx, specs):
+    sims = []
+    for sp in specs:
+        s = F.Sim(ctx, **sp)
+        s.init(1, 0.5)
+        sims.append(s)
+    return sims
+
+
+def _digest(s):
+    return hashlib.sha256(s.lattice().tobytes()).hexdigest(), s.observe()["events"]
+
+
+def _alone(F, ctx, specs):
+    out = []
+    for s in _make(F, ctx, specs):
+        s.run_to_end()
+        out.append(_digest(s))
+        s.close()
+    return out
+
+
+@pytest.mark.parametrize("K", [1, 3, 50])
+@pytest.mark.parametrize("graphs", [1, 0], ids=["graph", "eager"])
+def test_batch_persistent_equals_alone(F, ctx, K, graphs):
+    want = _alone(F, ctx, SPECS)
+    F.fskmc_ctx_set_batch_persistent(ctx, K)
+    F.fskmc_ctx_set_graphs(ctx, graphs)
+    sims = _make(F, ctx, SPECS)
+    handles = [s.handle for s in sims]
+    while any(s.windows()[1] < s.windows()[0] for s in sims):
+        F.fskmc_batch_advance(ctx, handles, 7)
+    F.fskmc_sync(ctx)
+    got = [_digest(s) for s in sims]
+    for s in sims:
+        s.close()
+    assert got == want
+
+
+@pytest.mark.parametrize("K", [0, 4])
+def test_graph_replays_match_eager(F, ctx, K):
+    """Two copies of one batch, one replaying a captured graph and one
+    launching eagerly, compared after every call (each call uploads a new job
+    table and synchronises between the replays)."""
+    F.fskmc_ctx_set_batch_persistent(ctx, K)
+    a = _make(F, ctx, SPECS[:4])
+    b = _make(F, ctx, SPECS[:4])
+    calls = 0
+    while any(s.windows()[1] < s.windows()[0] for s in a):
+        F.fskmc_ctx_set_graphs(ctx, 1)
+        F.fskmc_batch_advance(ctx, [s.handle for s in a], 5)
+        F.fskmc_sync(ctx)
+        F.fskmc_ctx_set_graphs(ctx, 0)
+        F.fskmc_batch_advance(ctx, [s.handle for s in b], 5)
+        F.fskmc_sync(ctx)
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x.lattice(), y.lattice())
+        calls += 1
+    assert calls >= 3
+    for s in a + b:
+        s.close()
+
+
+def test_batch_persistent_wait_timeout_reports_edevice(F, ctx):
+    """A wait limit far below one window forces the bounded neighbour wait to
+    give up: the launch aborts, every wave leaves, the next synchronising call
+    reports FSKMC_EDEVICE, and the context works again afterwards."""
+    F.fskmc_ctx_set_batch_persistent(ctx, 20)
+    sims = _make(F, ctx, SPECS[-1:])
+    F.fskmc_ctx_set_wait_limit(ctx, 1e-8)
+    try:
+        F.fskmc_batch_advance(ctx, [s.handle for s in sims], 10)
+        with pytest.raises(F.FskmcError) as ei:
+            F.fskmc_sync(ctx)
+        assert ei.value.code == F.FSKMC_EDEVICE
+    finally:
+        F.fskmc_ctx_set_wait_limit(ctx, 2.0)
+    for s in sims:
+        s.close()
+    want = _alone(F, ctx, SPECS[:1])
+    sims = _make(F, ctx, SPECS[:1])
+    while sims[0].windows()[1] < sims[0].windows()[0]:
+        F.fskmc_batch_advance(ctx, [sims[0].handle], 9)
+    F.fskmc_sync(ctx)
+    assert [_digest(sims[0])] == want
+    sims[0].close()
+
+
+def test_batch_knobs_invalid(F, ctx):
+    with pytest.raises(F.FskmcError) as ei:
+        F.fskmc_ctx_set_batch_persistent(ctx, -1)
+    assert ei.value.code == F.FSKMC_EINVAL
