@@ -21,8 +21,10 @@ Also in the JSON line:
   cpu_baseline  the oracle (plain single-threaded C, the blockwise scheme) on
                 a bounded sample of the same workload, on this host;
   batched       512 independent Ising replicas of mixed sizes (edges
-                128..1024) packed into one launch per window, against the same
-                512 runs advanced one after another, bit-identity checked;
+                128..1024) advanced together (one packed launch per window or
+                K windows per persistent launch, both autotuned with the waves
+                per workgroup), against the same 512 runs advanced one after
+                another, bit-identity checked;
   served        Poisson request streams (50, 200, 1000 jobs/s) of mixed Ising
                 and A/B reaction jobs (edges log-uniform in [64, 2048], T in
                 [10, 200]) served with continuous batching: p50/p99
@@ -90,6 +92,15 @@ def resident_bytes(b, block_windows, sites, launches):
     edge words are read and four written, and the 16-byte counter record is
     updated (28 bytes moved)."""
     return launches * 2 * sites + block_windows * (64 + 28)
+
+
+def nested_bytes(b, c, cells_per_launch, block_windows, launches):
+    """Algorithmic HBM bytes of the nested sweep (spin flip): per launch every
+    coarse cell of the active outer colour reads its c b x c b sites and the
+    one-site ring around them (without corners) once and writes its sites back
+    once; per block-window the 16-byte counter record is updated (28 bytes)."""
+    side = c * b
+    return launches * cells_per_launch * ((side + 2) ** 2 - 4 + side * side) + block_windows * 28
 
 
 def measured_traffic(symbol):
@@ -208,6 +219,8 @@ def bench_batched(F, ctx, n_jobs, stride, chunk=50):
 
     best, timings = autotune.tune_waves_per_group(ctx, lambda: make_all(jobs[:96]))
     log(f"autotune waves/group: {best} {timings}")
+    best_k, timings_k = autotune.tune_windows_per_launch(ctx, lambda: make_all(jobs[:96]))
+    log(f"autotune windows per launch: {best_k} {timings_k}")
     sims = make_all(jobs)
     handles = [s.handle for s in sims]
     F.fskmc_sync(ctx)
@@ -224,8 +237,12 @@ def bench_batched(F, ctx, n_jobs, stride, chunk=50):
     F.fskmc_sync(ctx)
     el = time.perf_counter() - t0
     obs = [s.observe() for s in sims]
-    rl = roofline(F, ctx, "flip", 16, obs, launches, "k_sweep_batched<P=4,flip>")
+    if best_k:
+        launches = -(-launches // best_k)
+    rl = roofline(F, ctx, "flip", 16, obs, launches,
+                  "k_sweep_batched_persistent<P=4,flip>" if best_k else "k_sweep_batched<P=4,flip>")
     F.fskmc_ctx_set_kernel_timing(ctx, 0)
+    F.fskmc_ctx_set_batch_persistent(ctx, 0)
     ev_b = sum(o["events"] for o in obs)
     dig_b = [hashlib.sha256(s.lattice().tobytes()).hexdigest() for s in sims]
     for s in sims:
@@ -251,7 +268,8 @@ def bench_batched(F, ctx, n_jobs, stride, chunk=50):
             "value": ev_b / el, "unit": "events/s", "seconds": el, "events": ev_b,
             "sequential_value": ev_s / el_s, "sequential_seconds": el_s,
             "speedup_vs_sequential": (ev_b / el) / (ev_s / el_s), "bit_identical_to_sequential": identical,
-            "waves_per_group": best, "autotune_s_per_window": timings, "roofline": rl}
+            "waves_per_group": best, "autotune_s_per_window": timings, "windows_per_launch": best_k,
+            "autotune_windows_per_launch_s_per_window": timings_k, "roofline": rl}
 
 
 def bench_balance(F, ctx, windows, chunk):
@@ -314,6 +332,7 @@ def bench_nested(F, ctx, T, dtau, c, stride):
             init_sim(s, wl)
             F.fskmc_sync(ctx)
             if knob:
+                F.fskmc_ctx_read_kernel_timing(ctx)  # discard
                 F.fskmc_ctx_set_kernel_timing(ctx, stride)
             t0 = time.perf_counter()
             s.run_to_end()
@@ -324,16 +343,29 @@ def bench_nested(F, ctx, T, dtau, c, stride):
                 F.fskmc_ctx_set_kernel_timing(ctx, 0)
             obs = s.observe()
             dig = hashlib.sha256(s.lattice().tobytes()).hexdigest()
-            launches = s.windows()[0]
+            windows = s.windows()[0]
             s.close()
             if best is None or el < best[0]:
-                best = (el, obs["events"], kms / max(kn, 1) if knob else None)
-        el, ev, kavg = best
+                best = (el, obs, (kms, kn) if knob else None)
+        el, obs, timing = best
+        ev = obs["events"]
         out[label] = {"value": ev / el, "seconds": el, "events": ev}
-        if kavg is not None:
-            out[label]["kernel_ms_avg"] = kavg
+        if timing is not None:
+            # outer windows = launches: the outer Lie scheme has 2 per step
+            launches = int(round(wl["T"] / wl["dt"])) * 2
+            cells = (wl["Lx"] // (c * wl["b"])) * (wl["Ly"] // (c * wl["b"])) // 2
+            per_launch = nested_bytes(wl["b"], c, cells, obs["block_windows"], launches) / launches
+            avg = timing[0] / 1e3 / max(timing[1], 1)
+            achieved = per_launch / avg / 1e9
+            P = wl["b"] ** 2 // 64
+            traffic, source = measured_traffic(f"k_sweep_nested<{P}, {wl['b']}, 1, {c}, 2>")
+            out[label]["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                                      "traffic_source": source, "kernel": f"k_sweep_nested<P={P},c={c}>",
+                                      "bytes_per_launch": per_launch, "avg_launch_us": avg * 1e6,
+                                      "timed_launches": timing[1], "launches": launches}
         digests.append(dig)
-        log(f"nested {label}: {ev / el:.3g} events/s ({el * 1e3:.1f} ms, {launches} windows)")
+        log(f"nested {label}: {ev / el:.3g} events/s ({el * 1e3:.1f} ms, {windows} windows)")
     F.fskmc_ctx_set_nested(ctx, 1)
     F.fskmc_ctx_set_persistent(ctx, 0)
     out["bit_identical"] = len(set(digests)) == 1

@@ -1638,7 +1638,7 @@ int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t 
                 if (e != hipSuccess)
                     break;
                 const LaunchTiming tk = timing_begin(ctx);
-                e = launch_sweep_batched_persistent(g.model, g.P, g.shape, ctx->wpg, a, grid, st, tk);
+                e = launch_sweep_batched_persistent(g.model, g.P, g.shape, ctx->wpg, a, 0, st, tk);
                 timing_end(ctx, tk);
                 if (e != hipSuccess)
                     break;

@@ -163,9 +163,11 @@ hipError_t launch_rebalance(const BlockCount* cnt, unsigned long long* ev_prev, 
                             const int8_t* win_colour, int pw0, int pw1, int first, unsigned long long base,
                             unsigned long long* scan, int32_t* owner, int nb, int use, int n_waves, int cap,
                             hipStream_t s);
+// grid == 0: as many workgroups as can be resident on the device.
 hipError_t launch_sweep_batched_persistent(int model, int P, int shape, int wpg, const BatchPersistArgs& a,
                                            unsigned grid, hipStream_t s, LaunchTiming tm);
-// Workgroups of one batched persistent launch that fill the device.
+// Lower bound of the resident workgroups of a batched persistent launch
+// (sizes the work chunks).
 unsigned batched_persistent_grid(int P, int shape, int wpg);
 hipError_t launch_epoch_init_batched(const JobDesc* jobs, int n_jobs, hipStream_t s);
 // Nested sweep variants: square coarse cells of c x c fine blocks of P*64

@@ -33,6 +33,8 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <utility>
+#include <vector>
 
 namespace fskmc {
 
@@ -1640,22 +1642,57 @@ hipError_t launch_sweep_batched(int model, int P, int shape, int wpg, const JobD
 #undef FSKMC_SW
 }
 
+// Workgroups of a kernel that can be resident at once on the device
+// (occupancy x CUs), cached per kernel; 0 when the runtime cannot say.
+template <typename K>
+static unsigned resident_grid(K kern, int threads)
+{
+    static std::vector<std::pair<const void*, unsigned>> cache;
+    for (auto& e : cache)
+        if (e.first == reinterpret_cast<const void*>(kern))
+            return e.second;
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    cache.emplace_back(reinterpret_cast<const void*>(kern), (unsigned)(per_cu * cus));
+    return (unsigned)(per_cu * cus);
+}
+
+// grid == 0: as many workgroups as can be resident (the work counter spreads
+// the items; more workgroups would only queue in the dispatcher)
+template <typename K>
+static hipError_t batched_persistent_launch(K kern, unsigned grid, int wpg, hipStream_t s, LaunchTiming tm,
+                                            const BatchPersistArgs& a)
+{
+    if (grid == 0)
+        grid = resident_grid(kern, 64 * wpg);
+    if (grid == 0)
+        grid = (unsigned)std::max(1, 2048 / wpg);
+    return launch(kern, dim3(grid), dim3(64 * wpg), s, tm, a);
+}
+
 template <int MODEL, int WPG>
 static hipError_t batched_persistent_dispatch(int P, int shape, const BatchPersistArgs& a, unsigned grid,
                                               hipStream_t s, LaunchTiming tm)
 {
-    const dim3 g(grid), b(64 * WPG);
     if (shape == SHAPE_SQ) {
         switch (P) {
-        case 1: return launch(k_sweep_batched_persistent<1, 8, 8, MODEL, WPG>, g, b, s, tm, a);
-        case 4: return launch(k_sweep_batched_persistent<4, 16, 16, MODEL, WPG>, g, b, s, tm, a);
-        case 16: return launch(k_sweep_batched_persistent<16, 32, 32, MODEL, WPG>, g, b, s, tm, a);
+        case 1: return batched_persistent_launch(k_sweep_batched_persistent<1, 8, 8, MODEL, WPG>, grid, WPG, s, tm, a);
+        case 4:
+            return batched_persistent_launch(k_sweep_batched_persistent<4, 16, 16, MODEL, WPG>, grid, WPG, s, tm, a);
+        case 16:
+            return batched_persistent_launch(k_sweep_batched_persistent<16, 32, 32, MODEL, WPG>, grid, WPG, s, tm, a);
         }
     } else if constexpr (MODEL == MODEL_FLIP) {
         switch (P) {
-        case 1: return launch(k_sweep_batched_persistent<1, 64, 1, MODEL, WPG>, g, b, s, tm, a);
-        case 4: return launch(k_sweep_batched_persistent<4, 256, 1, MODEL, WPG>, g, b, s, tm, a);
-        case 16: return launch(k_sweep_batched_persistent<16, 1024, 1, MODEL, WPG>, g, b, s, tm, a);
+        case 1: return batched_persistent_launch(k_sweep_batched_persistent<1, 64, 1, MODEL, WPG>, grid, WPG, s, tm, a);
+        case 4:
+            return batched_persistent_launch(k_sweep_batched_persistent<4, 256, 1, MODEL, WPG>, grid, WPG, s, tm, a);
+        case 16:
+            return batched_persistent_launch(k_sweep_batched_persistent<16, 1024, 1, MODEL, WPG>, grid, WPG, s, tm,
+                                             a);
         }
     }
     return hipErrorInvalidValue;
@@ -1664,7 +1701,7 @@ static hipError_t batched_persistent_dispatch(int P, int shape, const BatchPersi
 hipError_t launch_sweep_batched_persistent(int model, int P, int shape, int wpg, const BatchPersistArgs& a,
                                            unsigned grid, hipStream_t s, LaunchTiming tm)
 {
-    if (grid == 0 || a.chunk == 0 || a.s1 <= a.s0)
+    if (a.chunk == 0 || a.s1 <= a.s0)
         return hipErrorInvalidValue;
     if (model == MODEL_FLIP) {
         switch (wpg) {
@@ -1688,7 +1725,8 @@ unsigned batched_persistent_grid(int P, int shape, int wpg)
 {
     (void)P;
     (void)shape;
-    // 256 CUs x 8 waves; the queue balances the rest
+    // a lower bound of the resident workgroups (256 CUs x 8 waves) for the
+    // work-chunk size; the launch itself fills the device
     return (unsigned)std::max(1, 2048 / std::max(wpg, 1));
 }
 

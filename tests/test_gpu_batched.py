@@ -133,3 +133,11 @@ def test_batch_knobs_invalid(F, ctx):
     with pytest.raises(F.FskmcError) as ei:
         F.fskmc_ctx_set_batch_persistent(ctx, -1)
     assert ei.value.code == F.FSKMC_EINVAL
+
+
+def test_autotune_windows_per_launch_picks_a_candidate(F, ctx):
+    from paper_1105_4673_amd import autotune
+    best, timings = autotune.tune_windows_per_launch(ctx, lambda: _make(F, ctx, SPECS[:3]), candidates=(0, 5),
+                                                      windows=10)
+    assert best in (0, 5) and set(timings) == {0, 5} and all(t > 0 for t in timings.values())
+    F.fskmc_ctx_set_batch_persistent(ctx, 0)
