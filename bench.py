@@ -130,6 +130,9 @@ def roofline(F, ctx, kind, b, obs_list, launches, kernel_name, resident_sites=0,
     wr = sum(o["writes"] for o in obs_list)
     if resident_sites:
         bytes_per_launch = resident_bytes(b, bw, resident_sites, launches) / max(launches, 1)
+    elif isinstance(b, (list, tuple)):  # one block edge per simulation
+        total = sum(hbm_bytes(kind, bb, o["block_windows"], o["writes"]) for bb, o in zip(b, obs_list))
+        bytes_per_launch = total / max(launches, 1)
     else:
         bytes_per_launch = hbm_bytes(kind, b, bw, wr) / max(launches, 1)
     avg = ms_total / 1e3 / max(n_timed, 1)
@@ -217,6 +220,14 @@ def bench_batched(F, ctx, n_jobs, stride, chunk=50):
             out.append(s)
         return out
 
+    def make_b(j, b):
+        s = make_sim(F, ctx, dict(j, b=b))
+        init_sim(s, j)
+        return s
+
+    edges, edge_rates = autotune.tune_block_edges(ctx, jobs, make_b)
+    log(f"autotune block edge per size: {edges}")
+    jobs = [dict(j, b=edges[(j["Lx"], j["Ly"])]) for j in jobs]
     best, timings = autotune.tune_waves_per_group(ctx, lambda: make_all(jobs[:96]))
     log(f"autotune waves/group: {best} {timings}")
     best_k, timings_k = autotune.tune_windows_per_launch(ctx, lambda: make_all(jobs[:96]))
@@ -239,7 +250,7 @@ def bench_batched(F, ctx, n_jobs, stride, chunk=50):
     obs = [s.observe() for s in sims]
     if best_k:
         launches = -(-launches // best_k)
-    rl = roofline(F, ctx, "flip", 16, obs, launches,
+    rl = roofline(F, ctx, "flip", [j["b"] for j in jobs], obs, launches,
                   "k_sweep_batched_persistent<P=4,flip>" if best_k else "k_sweep_batched<P=4,flip>")
     F.fskmc_ctx_set_kernel_timing(ctx, 0)
     F.fskmc_ctx_set_batch_persistent(ctx, 0)
@@ -264,10 +275,15 @@ def bench_batched(F, ctx, n_jobs, stride, chunk=50):
     log(f"sequential: {ev_s} events in {el_s:.3f} s")
     identical = dig_b == dig_s and ev_b == ev_s
     sites = sum(j["Lx"] * j["Ly"] for j in jobs)
-    return {"workload": f"ising_x{n_jobs}_edges128-1024_b16_lie_dt0.1_T10", "jobs": n_jobs, "sites": sites,
+    bname = "b16" if all(j["b"] == 16 for j in jobs) else "bauto"
+    return {"workload": f"ising_x{n_jobs}_edges128-1024_{bname}_lie_dt0.1_T10", "jobs": n_jobs, "sites": sites,
             "value": ev_b / el, "unit": "events/s", "seconds": el, "events": ev_b,
             "sequential_value": ev_s / el_s, "sequential_seconds": el_s,
             "speedup_vs_sequential": (ev_b / el) / (ev_s / el_s), "bit_identical_to_sequential": identical,
+            "block_edge_by_size": {f"{k[0]}x{k[1]}": v for k, v in edges.items()},
+            "autotune_block_edge": {"chosen": edge_rates["chosen"], "assignments_events_per_s": edge_rates["assignments"],
+                                    "per_class_events_per_s": {f"{k[0]}x{k[1]}": r
+                                                               for k, r in edge_rates["per_class"].items()}},
             "waves_per_group": best, "autotune_s_per_window": timings, "windows_per_launch": best_k,
             "autotune_windows_per_launch_s_per_window": timings_k, "roofline": rl}
 

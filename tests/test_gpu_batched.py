@@ -141,3 +141,18 @@ def test_autotune_windows_per_launch_picks_a_candidate(F, ctx):
                                                       windows=10)
     assert best in (0, 5) and set(timings) == {0, 5} and all(t > 0 for t in timings.values())
     F.fskmc_ctx_set_batch_persistent(ctx, 0)
+
+
+def test_autotune_block_edges_returns_a_tiling_assignment(F, ctx):
+    from paper_1105_4673_amd import autotune
+    jobs = [dict(sp, replica=10 + i) for i, sp in enumerate(SPECS[:2] * 2)]
+
+    def make(j, b):
+        s = F.Sim(ctx, **dict(j, b=b))
+        s.init(1, 0.5)
+        return s
+
+    assign, scores = autotune.tune_block_edges(ctx, jobs, make, candidates=(8, 16), class_sample=2, sample=4,
+                                               windows=4)
+    assert set(assign) == {(128, 128), (256, 256)} and set(assign.values()) <= {8, 16}
+    assert scores["chosen"] in scores["assignments"] and {"per-class", "all-b8", "all-b16"} <= set(scores["assignments"])
