@@ -136,9 +136,7 @@ struct fskmc_sim {
     int32_t* d_next = nullptr;
     int32_t* d_nbr = nullptr;
     int32_t* d_epoch = nullptr;
-    // resident sweep: last window of each colour before w, tagged edge words
-    std::vector<int32_t> prev_part;  // [n_colours][n_windows+1]
-    int32_t* d_prev = nullptr;
+    // resident sweep: tagged edge words
     unsigned long long* d_edge = nullptr;
     // workload rebalancing: per-block events at the previous resident launch
     // and its windows, prefix-sum scratch, the block ranges of the last
@@ -451,7 +449,6 @@ void free_sim_device(fskmc_sim* S)
     (void)hipFree(S->d_next);
     (void)hipFree(S->d_nbr);
     (void)hipFree(S->d_epoch);
-    (void)hipFree(S->d_prev);
     (void)hipFree(S->d_edge);
     (void)hipFree(S->d_owner);
     (void)hipFree(S->d_cells);
@@ -704,7 +701,6 @@ int enqueue_resident(fskmc_sim* S, uint64_t w0, uint64_t w1)
     a.bcol = S->d_bcol;
     a.win_colour = S->d_wcol;
     a.win_dur = S->d_wdur;
-    a.prev_part = S->d_prev;
     a.edge = S->d_edge;
     a.abort_flag = c->d_abort;
     a.Lx = S->lat.Lx;
@@ -1187,10 +1183,6 @@ int sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const vo
     for (int c = 0; c < S->n_colours; ++c)
         for (int64_t w = (int64_t)S->n_windows - 1; w >= 0; --w)
             S->next_part[c * nw1 + w] = S->win_colour[w] == c ? (int32_t)w : S->next_part[c * nw1 + w + 1];
-    S->prev_part.assign((size_t)S->n_colours * nw1, -1);
-    for (int c = 0; c < S->n_colours; ++c)
-        for (uint64_t w = 0; w < S->n_windows; ++w)
-            S->prev_part[c * nw1 + w + 1] = S->win_colour[w] == c ? (int32_t)w : S->prev_part[c * nw1 + w];
     std::vector<int8_t> bcol(S->cmap.begin(), S->cmap.end());
     std::vector<int32_t> nbr;
     build_neighbours(*S, nbr);
@@ -1201,7 +1193,7 @@ int sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const vo
         (rc = dev_alloc(&S->d_coff, S->colour_off.size())) || (rc = dev_alloc(&S->d_wcol, S->n_windows)) ||
         (rc = dev_alloc(&S->d_wdur, S->n_windows)) || (rc = dev_alloc(&S->d_bcol, S->nb)) ||
         (rc = dev_alloc(&S->d_next, S->next_part.size())) || (rc = dev_alloc(&S->d_nbr, nbr.size())) ||
-        (rc = dev_alloc(&S->d_epoch, S->nb)) || (rc = dev_alloc(&S->d_prev, S->prev_part.size())) ||
+        (rc = dev_alloc(&S->d_epoch, S->nb)) ||
         (rc = dev_alloc(&S->d_edge, 4 * (size_t)S->nb)) || (rc = dev_alloc(&S->d_cells, S->cells.size()))) {
         free_sim_device(S);
         delete S;
@@ -1217,8 +1209,6 @@ int sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const vo
         e = hipMemcpyAsync(S->d_next, S->next_part.data(), S->next_part.size() * 4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(S->d_nbr, nbr.data(), nbr.size() * 4, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(S->d_prev, S->prev_part.data(), S->prev_part.size() * 4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(S->d_table, S->table.data(), S->table.size() * 8, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)

@@ -105,7 +105,6 @@ struct ResidentArgs {
     const int8_t* bcol;         // [n_blocks]: colour of each block
     const int8_t* win_colour;   // per window
     const double* win_dur;      // per window
-    const int32_t* prev_part;   // [n_colours][n_windows+1]: last window < w of colour c, -1 if none
     unsigned long long* edge;   // [n_blocks][4]: tag | bits << 32 of the first/last row, first/last column
     const int32_t* owner;       // [n_waves+1] block range of each wave, or null: wave g owns g*bpw .. +bpw-1
     int32_t* abort_flag;        // raised by a wave whose wait timed out

@@ -1044,13 +1044,22 @@ template <int P, int BX, int BY, int WPG, int BPW>
 __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
 {
     using C = Cfg<P, BX, BY, MODEL_FLIP>;
-    constexpr int WAVE = (BPW * C::TILE + C::NTAB * 8 + C::XFER + BPW * 16 + 15) / 16 * 16;
+    constexpr int KMAX = 128; // colours tracked per wave (the library allows at most 127)
+    constexpr int WAVE = (BPW * C::TILE + C::NTAB * 8 + C::XFER + 3 * BPW * 16 + KMAX * 4 + 15) / 16 * 16;
     __shared__ __attribute__((aligned(16))) uint8_t lds[WPG * WAVE];
     const int wid = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     uint8_t* wl = lds + wid * WAVE;
     double* tab = reinterpret_cast<double*>(wl + BPW * C::TILE);
     uint32_t* ledge = reinterpret_cast<uint32_t*>(wl + BPW * C::TILE + C::NTAB * 8 + C::XFER); // [BPW][4]
+    // per owned block and poll lane d (0 above, 1 below, 2 left, 3 right):
+    // the neighbour's block id, or -1 - i when this wave owns it as block i,
+    // and the neighbour's colour; then per colour the last window of that
+    // colour run so far in this launch (-1: none), so the tag a neighbour's
+    // edge must carry is an LDS read instead of two dependent global loads
+    int32_t* nbl = reinterpret_cast<int32_t*>(ledge + 4 * BPW); // [BPW][4]
+    int32_t* ncl = nbl + 4 * BPW;                               // [BPW][4]
+    int32_t* lastw = ncl + 4 * BPW;                             // [KMAX]
     const int gw = (int)xcd_order(blockIdx.x, gridDim.x) * WPG + wid;
     const int m0 = a.owner ? a.owner[gw] : gw * a.bpw;
     const int want_own = a.owner ? a.owner[gw + 1] - m0 : a.bpw;
@@ -1072,13 +1081,36 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
         cols |= (uint64_t)(uint8_t)a.bcol[m] << (8 * i);
         nown = i + 1;
     }
+    // lanes 0..3 poll the facing edge (index dd) of the block above, below,
+    // left, right
+    const bool active = lane < 4 && (C::DIM == 2 || lane >= 2);
+    const int dd = lane == 0 ? 1 : lane == 1 ? 0 : lane == 2 ? 3 : 2;
+    for (int i = 0; i < nown; ++i) {
+        if (active) {
+            const int m = m0 + i;
+            const int bi = m % a.NBX, bj = m / a.NBX;
+            int nbm;
+            if (lane == 0)
+                nbm = (bj == 0 ? a.NBY - 1 : bj - 1) * a.NBX + bi;
+            else if (lane == 1)
+                nbm = (bj + 1 == a.NBY ? 0 : bj + 1) * a.NBX + bi;
+            else if (lane == 2)
+                nbm = bj * a.NBX + (bi == 0 ? a.NBX - 1 : bi - 1);
+            else
+                nbm = bj * a.NBX + (bi + 1 == a.NBX ? 0 : bi + 1);
+            const bool local = nbm >= m0 && nbm < m0 + nown; // owned by this wave: LDS copy
+            nbl[4 * i + lane] = local ? -1 - (nbm - m0) : nbm;
+            ncl[4 * i + lane] = (uint8_t)a.bcol[nbm];
+        }
+    }
+    for (int k = lane; k < KMAX; k += 64)
+        lastw[k] = -1;
     wave_sync();
 #pragma unroll 1
     for (int i = 0; i < nown; ++i)
         publish_edges<P, BX, BY>(wl + i * C::TILE, tb, a.edge + 4 * (size_t)(m0 + i), ledge + 4 * i,
                                  (uint32_t)a.w0, lane, r, c0);
 
-    const int nw1 = a.n_windows + 1;
 #pragma unroll 1
     for (int w = a.w0; w < a.w1; ++w) {
         const int c = a.win_colour[w];
@@ -1088,34 +1120,17 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
                 continue;
             const int m = m0 + i;
             uint8_t* tile = wl + i * C::TILE;
-            const int bi = m % a.NBX, bj = m / a.NBX;
-            // lanes 0..3 poll the facing edge of the block above, below, left, right
-            const bool active = lane < 4 && (C::DIM == 2 || lane >= 2);
-            int nbm = m, dd = 0;
-            if (lane == 0) {
-                nbm = (bj == 0 ? a.NBY - 1 : bj - 1) * a.NBX + bi;
-                dd = 1;
-            } else if (lane == 1) {
-                nbm = (bj + 1 == a.NBY ? 0 : bj + 1) * a.NBX + bi;
-                dd = 0;
-            } else if (lane == 2) {
-                nbm = bj * a.NBX + (bi == 0 ? a.NBX - 1 : bi - 1);
-                dd = 3;
-            } else if (lane == 3) {
-                nbm = bj * a.NBX + (bi + 1 == a.NBX ? 0 : bi + 1);
-                dd = 2;
-            }
-            const unsigned long long* src = a.edge + 4 * (size_t)nbm + dd;
-            const bool local = nbm >= m0 && nbm < m0 + nown; // owned by this wave: LDS copy
             unsigned long long v = 0;
             uint32_t want = 0;
+            const int nb = active ? nbl[4 * i + lane] : -1;
+            const unsigned long long* src = a.edge + 4 * (size_t)(nb < 0 ? 0 : nb) + dd;
             if (active) {
-                if (local) {
-                    v = (unsigned long long)ledge[4 * (nbm - m0) + dd] << 32;
+                if (nb < 0) {
+                    v = (unsigned long long)ledge[4 * (-1 - nb) + dd] << 32;
                 } else {
                     v = coh_load(src);
-                    const int last = a.prev_part[a.bcol[nbm] * nw1 + w];
-                    want = last >= a.w0 ? (uint32_t)last + 1u : (uint32_t)a.w0;
+                    const int last = lastw[ncl[4 * i + lane]];
+                    want = last >= 0 ? (uint32_t)last + 1u : (uint32_t)a.w0;
                 }
             }
             // this lane's first draw of the window, computed while the poll is in flight
@@ -1123,7 +1138,7 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
             const double nl0 = -fs_log(unif_open0(rr));
             const double v0 = unif_open1(rr);
             bool bad = false;
-            if (active && !local && (uint32_t)v != want) {
+            if (active && nb >= 0 && (uint32_t)v != want) {
                 const uint64_t t0 = wall_clock64();
                 for (uint32_t n = 1;; ++n) {
                     __builtin_amdgcn_s_sleep(1);
@@ -1173,6 +1188,9 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
                 }
             }
         }
+        if (lane == 0)
+            lastw[c] = w;
+        wave_sync();
     }
 #pragma unroll 1
     for (int i = 0; i < nown; ++i) {
