@@ -585,6 +585,16 @@ __device__ __forceinline__ int descend(const Tree<P>& T, double tg, int lane, do
 // into the tile at the end; pair events update the tile in place.
 // Returns the number of accepted events.  With `pre`, (nl0, v0) are this
 // lane's -log U and V of draw e = lane, computed by the caller ahead of time.
+// Draws e0 .. e0+63 of block m in window w, one per lane: (-log U, V).  Not
+// inlined: the event loop then keeps none of the generator's and the
+// logarithm's constants live (they pushed the kernel arguments out of the
+// scalar registers into spill lanes, reloaded every window).
+__device__ __noinline__ double2 draw_batch(uint32_t e0, uint32_t m, uint32_t w, uint32_t k0, uint32_t k1)
+{
+    const uint4 rr = philox10(make_uint4(e0 + (uint32_t)(threadIdx.x & 63), m, w, 0u), k0, k1);
+    return make_double2(-fs_log(unif_open0(rr)), unif_open1(rr));
+}
+
 // TS: row stride of the tile (the block's own tile by default; a larger
 // shared tile when several waves hold the sub-blocks of one coarse cell, in
 // which case `tile` points at the sub-block's origin minus one row and P columns).
@@ -609,17 +619,20 @@ __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const
     double t = 0.0;
     uint32_t e = 0, e0 = 0;
     double nl_b = nl0, v_b = v0; // this lane's draw e0 + lane: -log U and V
-    bool have_batch = pre;
+    if (!pre && uniform_f64(T.R) != 0.0) {
+        const uint4 rr = philox10(make_uint4((uint32_t)lane, m, w, 0u), k0, k1);
+        nl_b = -fs_log(unif_open0(rr));
+        v_b = unif_open1(rr);
+    }
     for (;;) {
         const double R = uniform_f64(T.R);
         if (R == 0.0)
             break;
-        if (!have_batch || e - e0 >= 64u) {
-            e0 = have_batch ? e : 0u;
-            have_batch = true;
-            const uint4 rr = philox10(make_uint4(e0 + (uint32_t)lane, m, w, 0u), k0, k1);
-            nl_b = -fs_log(unif_open0(rr));
-            v_b = unif_open1(rr);
+        if (e - e0 >= 64u) { // rare: a window with more than 64 events
+            e0 = e;
+            const double2 d = draw_batch(e0, m, w, k0, k1);
+            nl_b = d.x;
+            v_b = d.y;
         }
         const int k = (int)(e - e0);
         const double nl = readlane_f64(nl_b, k);
