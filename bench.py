@@ -53,6 +53,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "KMC events/sec on 1 MI355X (plain vs batched/served) at bit-exact oracle match"
 HBM_PEAK_GBS = 8000.0
+LDS_PEAK_GBS = 128 * 256 * 2.4  # 128 B/clk per CU, 256 CUs, 2.4 GHz = 78.6 TB/s
 
 
 def log(msg):
@@ -92,6 +93,23 @@ def resident_bytes(b, block_windows, sites, launches):
     edge words are read and four written, and the 16-byte counter record is
     updated (28 bytes moved)."""
     return launches * 2 * sites + block_windows * (64 + 28)
+
+
+def lds_bytes(kind, b, block_windows, events, resident=False):
+    """Algorithmic LDS bytes of the method with the block's sum tree in LDS:
+    per block-window the staged block and halo (the halo only when the
+    blocks stay resident), the leaves written (8n) and the n-1 inner nodes
+    built from two children each (24 bytes); per accepted event a descent
+    reading both children on log2 n levels (16 log2 n) and the dirty paths,
+    bounded by 5 leaves (spin flip: the site and its four neighbours) or 8
+    (pair events) of 8 + 24 log2 n bytes each.  The kernels here keep the
+    tree in registers, so this is the method's figure, not the traffic."""
+    import math
+    n = b * b
+    lg = math.log2(n)
+    stage = 4 * b if resident else n + 4 * b
+    dirty = 5 if kind == "flip" else 8
+    return block_windows * (stage + 8 * n + 24 * (n - 1)) + events * (16 * lg + dirty * (8 + 24 * lg))
 
 
 def nested_bytes(b, c, cells_per_launch, block_windows, launches):
@@ -138,9 +156,18 @@ def roofline(F, ctx, kind, b, obs_list, launches, kernel_name, resident_sites=0,
     avg = ms_total / 1e3 / max(n_timed, 1)
     achieved = bytes_per_launch / avg / 1e9 if n_timed else 0.0
     traffic, source = measured_traffic(symbol)
+    ev = sum(o["events"] for o in obs_list)
+    if isinstance(b, (list, tuple)):
+        lds = sum(lds_bytes(kind, bb, o["block_windows"], o["events"]) for bb, o in zip(b, obs_list))
+    else:
+        lds = lds_bytes(kind, b, bw, ev, resident=bool(resident_sites))
+    lds_per_launch = lds / max(launches, 1)
+    lds_achieved = lds_per_launch / avg / 1e9 if n_timed else 0.0
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": source, "kernel": kernel_name,
-            "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg * 1e6, "timed_launches": n_timed}
+            "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg * 1e6, "timed_launches": n_timed,
+            "lds": {"bound": "lds", "achieved": lds_achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                    "frac": lds_achieved / LDS_PEAK_GBS, "bytes_per_launch": lds_per_launch}}
 
 
 def bench_plain(F, ctx, wl, steps, warmup, stride, persist=0, resident=False, wpg=2):
