@@ -278,7 +278,8 @@ int fskmc_ctx_set_persistent(fskmc_ctx* ctx, int windows);
  * simulations keep every block in LDS for the whole launch and exchange only
  * the blocks' one-site boundary layers between windows (Sec. 2.2, local
  * synchronisation), when the blocks fit the waves resident on the device (at
- * most four blocks per wave); otherwise, and for the reaction model, the
+ * most eight blocks of 8x8 or 16x16 sites, or four of 32x32, per wave);
+ * otherwise, and for the pair-event models, the
  * persistent sweep streams each block from HBM every window.  After a
  * persistent sweep returns FSKMC_EDEVICE the lattice contents are unspecified. */
 int fskmc_ctx_set_resident(fskmc_ctx* ctx, int on);
