@@ -54,6 +54,8 @@ sys.path.insert(0, ROOT)
 METRIC = "KMC events/sec on 1 MI355X (plain vs batched/served) at bit-exact oracle match"
 HBM_PEAK_GBS = 8000.0
 LDS_PEAK_GBS = 128 * 256 * 2.4  # 128 B/clk per CU, 256 CUs, 2.4 GHz = 78.6 TB/s
+# VALU issue: 256 CUs x 4 SIMDs x 2.4e9 cycles/s, one wave64 instruction per 4 cycles per SIMD
+VALU_PEAK_GINST = 256 * 4 * 2.4 / 4
 
 
 def log(msg):
@@ -121,6 +123,23 @@ def nested_bytes(b, c, cells_per_launch, block_windows, launches):
     return launches * cells_per_launch * ((side + 2) ** 2 - 4 + side * side) + block_windows * 28
 
 
+def measured_valu(symbol):
+    """VALU wave-instructions per launch of `symbol` (rocprofv3 SQ_INSTS_VALU,
+    recorded in profiles/valu.json for the workload the bench runs), or None
+    when there is no record or the kernel source has changed since."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "valu.json")) as f:
+            rec = json.load(f)["kernels"].get(symbol)
+        with open(os.path.join(ROOT, "paper_1105_4673_amd", "csrc", "fskmc_kernels.hip"), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError, KeyError):
+        return None, None
+    if not rec or rec.get("kernel_source_sha256") != sha:
+        return None, None
+    return rec["valu_per_dispatch"], rec["source"]
+
+
 def measured_traffic(symbol):
     """HBM bytes per launch of `symbol` from the rocprofv3 FETCH_SIZE /
     WRITE_SIZE passes recorded in profiles/hbm_traffic.json (scaled by the
@@ -167,7 +186,20 @@ def roofline(F, ctx, kind, b, obs_list, launches, kernel_name, resident_sites=0,
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": source, "kernel": kernel_name,
             "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg * 1e6, "timed_launches": n_timed,
             "lds": {"bound": "lds", "achieved": lds_achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                    "frac": lds_achieved / LDS_PEAK_GBS, "bytes_per_launch": lds_per_launch}}
+                    "frac": lds_achieved / LDS_PEAK_GBS, "bytes_per_launch": lds_per_launch},
+            "alu": alu_term(symbol, avg if n_timed else 0.0)}
+
+
+def alu_term(symbol, avg_s):
+    """Measured VALU issue rate of a launch against the chip's issue peak
+    (recorded SQ_INSTS_VALU per launch over the measured launch duration): a
+    utilisation of the SIMDs, not an algorithmic operation count."""
+    valu, source = measured_valu(symbol) if symbol else (None, None)
+    if valu is None or avg_s <= 0:
+        return None
+    achieved = valu / avg_s / 1e9
+    return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GINST, "unit": "Ginst/s",
+            "frac": achieved / VALU_PEAK_GINST, "valu_per_launch": valu, "valu_source": source}
 
 
 def bench_plain(F, ctx, wl, steps, warmup, stride, persist=0, resident=False, wpg=2):
@@ -232,7 +264,7 @@ def cpu_baseline(wl, seconds):
                       f"single-threaded, {events} events in {el:.1f} s CPU"}
 
 
-def bench_batched(F, ctx, n_jobs, stride, chunk=50):
+def bench_batched(F, ctx, n_jobs, stride, chunk=50, wpg=0, k=-1, sequential=True):
     """512 (n_jobs) Ising replicas in one packed launch per window vs the same
     replicas advanced one at a time; every job's final lattice compared."""
     import hashlib
@@ -255,10 +287,18 @@ def bench_batched(F, ctx, n_jobs, stride, chunk=50):
     edges, edge_rates = autotune.tune_block_edges(ctx, jobs, make_b)
     log(f"autotune block edge per size: {edges}")
     jobs = [dict(j, b=edges[(j["Lx"], j["Ly"])]) for j in jobs]
-    best, timings = autotune.tune_waves_per_group(ctx, lambda: make_all(jobs[:96]))
-    log(f"autotune waves/group: {best} {timings}")
-    best_k, timings_k = autotune.tune_windows_per_launch(ctx, lambda: make_all(jobs[:96]))
-    log(f"autotune windows per launch: {best_k} {timings_k}")
+    if wpg:
+        best, timings = wpg, None
+        F.fskmc_ctx_set_waves_per_group(ctx, wpg)
+    else:
+        best, timings = autotune.tune_waves_per_group(ctx, lambda: make_all(jobs[:96]))
+    log(f"waves/group: {best} {timings}")
+    if k >= 0:
+        best_k, timings_k = k, None
+        F.fskmc_ctx_set_batch_persistent(ctx, k)
+    else:
+        best_k, timings_k = autotune.tune_windows_per_launch(ctx, lambda: make_all(jobs[:96]))
+    log(f"windows per launch: {best_k} {timings_k}")
     sims = make_all(jobs)
     handles = [s.handle for s in sims]
     F.fskmc_sync(ctx)
@@ -277,8 +317,11 @@ def bench_batched(F, ctx, n_jobs, stride, chunk=50):
     obs = [s.observe() for s in sims]
     if best_k:
         launches = -(-launches // best_k)
+    P = jobs[0]["b"] ** 2 // 64
+    symbol = None if best_k or any(j["b"] != jobs[0]["b"] for j in jobs) else \
+        f"k_sweep_batched<{P}, {jobs[0]['b']}, {jobs[0]['b']}, 1, {best}>"
     rl = roofline(F, ctx, "flip", [j["b"] for j in jobs], obs, launches,
-                  "k_sweep_batched_persistent<P=4,flip>" if best_k else "k_sweep_batched<P=4,flip>")
+                  "k_sweep_batched_persistent<P=4,flip>" if best_k else "k_sweep_batched<P=4,flip>", symbol=symbol)
     F.fskmc_ctx_set_kernel_timing(ctx, 0)
     F.fskmc_ctx_set_batch_persistent(ctx, 0)
     ev_b = sum(o["events"] for o in obs)
@@ -287,26 +330,30 @@ def bench_batched(F, ctx, n_jobs, stride, chunk=50):
         s.close()
     log(f"batched: {ev_b} events in {el:.3f} s")
 
-    seq = make_all(jobs)
-    F.fskmc_sync(ctx)
-    t0 = time.perf_counter()
-    for s in seq:
-        s.run_to_end()
-    F.fskmc_sync(ctx)
-    el_s = time.perf_counter() - t0
-    obs_s = [s.observe() for s in seq]
-    ev_s = sum(o["events"] for o in obs_s)
-    dig_s = [hashlib.sha256(s.lattice().tobytes()).hexdigest() for s in seq]
-    for s in seq:
-        s.close()
-    log(f"sequential: {ev_s} events in {el_s:.3f} s")
-    identical = dig_b == dig_s and ev_b == ev_s
+    if sequential:
+        seq = make_all(jobs)
+        F.fskmc_sync(ctx)
+        t0 = time.perf_counter()
+        for s in seq:
+            s.run_to_end()
+        F.fskmc_sync(ctx)
+        el_s = time.perf_counter() - t0
+        obs_s = [s.observe() for s in seq]
+        ev_s = sum(o["events"] for o in obs_s)
+        dig_s = [hashlib.sha256(s.lattice().tobytes()).hexdigest() for s in seq]
+        for s in seq:
+            s.close()
+        log(f"sequential: {ev_s} events in {el_s:.3f} s")
+        identical = dig_b == dig_s and ev_b == ev_s
+    else:  # counter runs: the 10^5 sequential launches are not needed
+        el_s, ev_s, identical = None, None, None
     sites = sum(j["Lx"] * j["Ly"] for j in jobs)
     bname = "b16" if all(j["b"] == 16 for j in jobs) else "bauto"
     return {"workload": f"ising_x{n_jobs}_edges128-1024_{bname}_lie_dt0.1_T10", "jobs": n_jobs, "sites": sites,
             "value": ev_b / el, "unit": "events/s", "seconds": el, "events": ev_b,
-            "sequential_value": ev_s / el_s, "sequential_seconds": el_s,
-            "speedup_vs_sequential": (ev_b / el) / (ev_s / el_s), "bit_identical_to_sequential": identical,
+            "sequential_value": ev_s / el_s if sequential else None, "sequential_seconds": el_s if sequential else None,
+            "speedup_vs_sequential": (ev_b / el) / (ev_s / el_s) if sequential else None,
+            "bit_identical_to_sequential": identical,
             "block_edge_by_size": {f"{k[0]}x{k[1]}": v for k, v in edges.items()},
             "autotune_block_edge": {"chosen": edge_rates["chosen"], "assignments_events_per_s": edge_rates["assignments"],
                                     "per_class_events_per_s": {f"{k[0]}x{k[1]}": r
@@ -466,6 +513,12 @@ def main():
     ap.add_argument("--balance-windows", type=int, default=200,
                     help="windows of the half-filled 2048^2 rebalancing comparison; 0 skips it")
     ap.add_argument("--balance-chunk", type=int, default=20)
+    ap.add_argument("--batched-wpg", type=int, default=0,
+                    help="waves per workgroup of the batched launches (0: autotuned)")
+    ap.add_argument("--batched-windows-per-launch", type=int, default=-1,
+                    help="windows per batched launch (0: one packed launch per window; -1: autotuned)")
+    ap.add_argument("--batched-sequential", type=int, default=1,
+                    help="0 skips the sequential comparison of the batched measurement")
     ap.add_argument("--nested-T", type=float, default=20.0, help="0 skips the nested measurement")
     ap.add_argument("--nested-dtau", type=float, default=0.05)
     ap.add_argument("--nested-cell", type=int, default=4)
@@ -548,7 +601,9 @@ def main():
     F.fskmc_ctx_set_persistent(ctx, 0)  # batched and served runs use one packed launch per window
     if args.batched_jobs:
         F.fskmc_ctx_set_waves_per_group(ctx, args.waves_per_group)
-        result["batched"] = bench_batched(F, ctx, args.batched_jobs, args.timing_stride)
+        result["batched"] = bench_batched(F, ctx, args.batched_jobs, args.timing_stride, wpg=args.batched_wpg,
+                                          k=args.batched_windows_per_launch,
+                                          sequential=bool(args.batched_sequential))
     if args.served_jobs:
         F.fskmc_ctx_set_waves_per_group(ctx, args.waves_per_group)
         result["served"] = bench_served(F, ctx, [float(r) for r in args.served_rates.split(",")], args.served_jobs,
