@@ -183,8 +183,13 @@ int fskmc_sim_destroy(fskmc_sim* sim);
  * square cells of 2 x 2 or 4 x 4 blocks (spin flip, 2 inner colours; or 4 x 4
  * blocks with 4; pair models 2 x 2 or 4 x 4 blocks with 4 inner colours) run
  * one launch per outer window, one workgroup per coarse cell, every inner
- * window inside it; other shapes, or fskmc_ctx_set_nested(ctx, 0), run the
- * flat sweeps on the same window list (same bits). */
+ * window inside it; for spin flip with fskmc_ctx_set_persistent(ctx, K > 0)
+ * and the resident knob on, K windows run in one launch in which every cell
+ * stays a resident workgroup and neighbouring cells exchange their one-site
+ * boundary layers through tagged words between outer windows (when all
+ * cells fit the device at once; waits are bounded as for the persistent
+ * sweeps).  Other shapes, or fskmc_ctx_set_nested(ctx, 0), run the flat
+ * sweeps on the same window list (same bits). */
 int fskmc_sim_create_nested(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const void* params,
                             const fskmc_nested* nested, const fskmc_schedule* schedule, fskmc_key key,
                             fskmc_sim** out);
@@ -300,8 +305,8 @@ int fskmc_ctx_set_rebalance(fskmc_ctx* ctx, int on);
  * cells have a GPU variant advance one launch per outer window (one workgroup
  * per coarse cell, the inner windows separated by workgroup barriers); off,
  * they use the flat sweeps (one launch per window, or the persistent sweeps)
- * on the same window list.  The persistent setting does not apply to the
- * nested launches. */
+ * on the same window list.  With the persistent setting, spin-flip nested
+ * sims use resident launches (see fskmc_sim_create_nested). */
 int fskmc_ctx_set_nested(fskmc_ctx* ctx, int on);
 
 /* Workload histogram (Sec. 5, eq. wload): out[m] = accepted events of block m

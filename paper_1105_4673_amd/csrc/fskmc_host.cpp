@@ -156,7 +156,9 @@ struct fskmc_sim {
     double dtau = 0.0;
     std::vector<int32_t> cells, cell_off;
     std::vector<uint32_t> outer_end;
+    std::vector<int32_t> ofirst, oidx;  // first window of each outer window (+ end); outer window of each window
     int32_t* d_cells = nullptr;
+    int32_t* d_ofirst = nullptr;
 };
 
 namespace {
@@ -339,6 +341,8 @@ int build_nested_schedule(fskmc_sim& S)
     S.win_dur.clear();
     S.step_end.clear();
     S.outer_end.clear();
+    S.ofirst.clear();
+    S.oidx.clear();
     for (size_t k = 0; k < oc.size(); ++k) {
         const size_t first = S.win_colour.size();
         if ((rc = scheme_windows(S.inner_split, S.k_inner, S.dtau, od[k], S.key, first, S.win_colour, S.win_dur,
@@ -351,7 +355,10 @@ int build_nested_schedule(fskmc_sim& S)
         }
         S.step_end.back() = oe[k];
         S.outer_end.resize(S.win_colour.size(), (uint32_t)S.win_colour.size());
+        S.ofirst.push_back((int32_t)first);
+        S.oidx.resize(S.win_colour.size(), (int32_t)k);
     }
+    S.ofirst.push_back((int32_t)S.win_colour.size());
     S.n_windows = S.win_colour.size();
     return FSKMC_OK;
 }
@@ -452,6 +459,7 @@ void free_sim_device(fskmc_sim* S)
     (void)hipFree(S->d_edge);
     (void)hipFree(S->d_owner);
     (void)hipFree(S->d_cells);
+    (void)hipFree(S->d_ofirst);
     (void)hipFree(S->d_ev_prev);
     (void)hipFree(S->d_scan);
     S->d_lat = nullptr;
@@ -538,6 +546,55 @@ int enqueue_nested(fskmc_sim* S, uint64_t w0, uint64_t w1)
     HIP_TRY(launch_sweep_nested(kernel_model(S->model), S->P, S->cx, S->k_inner, a, S->ctx->stream, tk));
     timing_end(S->ctx, tk);
     S->block_windows += (w1 - w0) * (uint64_t)a.n_cells * (uint64_t)(S->cx * S->cy / S->k_inner);
+    return FSKMC_OK;
+}
+
+// Windows [w0, w1) of a nested spin-flip sim in one resident launch: 1 when
+// the cells cannot all be resident at once (the caller launches per outer
+// window instead).
+int enqueue_nested_resident(fskmc_sim* S, uint64_t w0, uint64_t w1)
+{
+    fskmc_ctx* c = S->ctx;
+    hipStream_t st = c->stream;
+    const int cs = S->cx * S->bx;
+    const int64_t words = (int64_t)S->NCX * S->NCY * (cs / 8);
+    HIP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(S->d_edge), words, ~0ull, st));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_abort), 1, 0u, st));
+    NestedResArgs a{};
+    a.lat = S->d_lat;
+    a.table = S->d_table;
+    a.cnt = S->d_cnt;
+    a.win_colour = S->d_wcol;
+    a.win_dur = S->d_wdur;
+    a.ofirst = S->d_ofirst;
+    a.edge = S->d_edge;
+    a.abort_flag = c->d_abort;
+    a.Lx = S->lat.Lx;
+    a.Ly = S->lat.Ly;
+    a.NBX = S->NBX;
+    a.NCX = S->NCX;
+    a.NCY = S->NCY;
+    a.k_outer = S->k_outer;
+    a.k0 = S->key.seed;
+    a.k1 = S->key.replica;
+    a.w0 = (int)w0;
+    a.w1 = (int)w1;
+    a.ow0 = S->oidx[w0];
+    a.ow1 = S->oidx[w1 - 1] + 1;
+    a.wait_ticks = c->wait_ticks;
+    const LaunchTiming tk = timing_begin(c);
+    const hipError_t e = launch_sweep_nested_resident(S->P, S->cx, S->k_inner, a, st, tk);
+    if (e == hipErrorInvalidConfiguration) {
+        timing_end(c, LaunchTiming{});
+        return 1;
+    }
+    HIP_TRY(e);
+    timing_end(c, tk);
+    HIP_TRY(hipMemcpyAsync(c->h_abort, c->d_abort, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    for (uint64_t w = w0; w < w1; ++w) {
+        const int co = S->win_colour[w] / S->k_inner;
+        S->block_windows += (uint64_t)(S->cell_off[co + 1] - S->cell_off[co]) * (uint64_t)(S->cx * S->cy / S->k_inner);
+    }
     return FSKMC_OK;
 }
 
@@ -1194,7 +1251,8 @@ int sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const vo
         (rc = dev_alloc(&S->d_wdur, S->n_windows)) || (rc = dev_alloc(&S->d_bcol, S->nb)) ||
         (rc = dev_alloc(&S->d_next, S->next_part.size())) || (rc = dev_alloc(&S->d_nbr, nbr.size())) ||
         (rc = dev_alloc(&S->d_epoch, S->nb)) ||
-        (rc = dev_alloc(&S->d_edge, 4 * (size_t)S->nb)) || (rc = dev_alloc(&S->d_cells, S->cells.size()))) {
+        (rc = dev_alloc(&S->d_edge, 4 * (size_t)S->nb)) || (rc = dev_alloc(&S->d_cells, S->cells.size())) ||
+        (rc = dev_alloc(&S->d_ofirst, S->ofirst.size()))) {
         free_sim_device(S);
         delete S;
         return rc;
@@ -1205,6 +1263,8 @@ int sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const vo
         e = hipMemcpyAsync(S->d_bcol, bcol.data(), bcol.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && !S->cells.empty())
         e = hipMemcpyAsync(S->d_cells, S->cells.data(), S->cells.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !S->ofirst.empty())
+        e = hipMemcpyAsync(S->d_ofirst, S->ofirst.data(), S->ofirst.size() * 4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(S->d_next, S->next_part.data(), S->next_part.size() * 4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
@@ -1326,7 +1386,19 @@ int fskmc_sim_advance(fskmc_sim* S, uint64_t n_windows)
         return fail(FSKMC_ESTATE, "only %llu windows left before T", (unsigned long long)(S->n_windows - S->window));
     if (S->nested && S->nest_kernel_ok && S->ctx->nested_kernel) {
         const uint64_t end = S->window + n_windows;
+        fskmc_ctx* c = S->ctx;
+        const bool resident = c->persist > 0 && c->resident && S->model == FSKMC_MODEL_FLIP;
         while (S->window < end) {
+            if (resident) {
+                const uint64_t w1 = std::min<uint64_t>(end, S->window + (uint64_t)c->persist);
+                const int rc = enqueue_nested_resident(S, S->window, w1);
+                if (rc == FSKMC_OK) {
+                    S->window = w1;
+                    continue;
+                }
+                if (rc != 1)
+                    return rc;
+            }
             const uint64_t w1 = std::min<uint64_t>(end, S->outer_end[S->window]);
             if (int rc = enqueue_nested(S, S->window, w1))
                 return rc;

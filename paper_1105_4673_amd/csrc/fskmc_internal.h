@@ -169,6 +169,29 @@ hipError_t launch_sweep_batched_persistent(int model, int P, int shape, int wpg,
 // (sizes the work chunks).
 unsigned batched_persistent_grid(int P, int shape, int wpg);
 hipError_t launch_epoch_init_batched(const JobDesc* jobs, int n_jobs, hipStream_t s);
+// Resident nested sweep (spin flip): every coarse cell is one workgroup for
+// the whole launch and keeps its tile in LDS; between outer windows the
+// cells exchange their one-site boundary layers through tagged words.
+struct NestedResArgs {
+    uint8_t* lat;
+    const double* table;
+    BlockCount* cnt;
+    const int8_t* win_colour;
+    const double* win_dur;
+    const int32_t* ofirst;    // first window of each outer window, n_outer + 1 entries
+    unsigned long long* edge; // cells x (cell side / 8) tagged words
+    int32_t* abort_flag;
+    int Lx, Ly, NBX, NCX, NCY, k_outer;
+    uint32_t k0, k1;
+    int w0, w1;               // windows of this launch
+    int ow0, ow1;             // the outer windows they fall in
+    unsigned long long wait_ticks;
+};
+// hipErrorInvalidConfiguration when the cells do not fit the device at once
+// (the caller then launches per outer window).
+hipError_t launch_sweep_nested_resident(int P, int c, int k_inner, const NestedResArgs& a, hipStream_t s,
+                                        LaunchTiming tm);
+
 // Nested sweep variants: square coarse cells of c x c fine blocks of P*64
 // sites with k_inner inner colours; nested_supported() says which exist.
 bool nested_supported(int model, int P, int c, int k_inner);

@@ -1355,6 +1355,150 @@ __global__ __launch_bounds__(64 * (CC * CC / KI)) void k_sweep_nested(NestedArgs
     }
 }
 
+// Resident nested sweep (spin flip; Sec. 6 with the local synchronisation of
+// Sec. 2.2 at the coarse level).  Every coarse cell is one workgroup for the
+// whole launch and keeps its tile in LDS; the lattice is read once at the
+// start and written once at the end.  The cell's four one-site boundary
+// layers (4 x CS sites, listed top row, bottom row, left column, right
+// column) are published as bits, 32 per 64-bit word tagged with the outer
+// window just finished + 1 (ow0 at the start).  Before a cell runs its part
+// of outer window k, wave 0 polls the words of its four neighbours that hold
+// the layers facing it until each carries the tag of that neighbour's last
+// outer window before k (same argument as the block-level resident sweep:
+// tag and bits travel in one word, and a word is only overwritten after its
+// readers have moved on), the ring is rebuilt from them, and the inner windows
+// run as in the per-launch nested sweep.  Waits are bounded by wait_ticks.
+template <int P, int B, int CC, int KI>
+__global__ __launch_bounds__(64 * (CC * CC / KI)) void k_sweep_nested_resident(NestedResArgs a)
+{
+    using N = NestCfg<P, B, MODEL_FLIP, CC, KI>;
+    using C = Cfg<P, B, B, MODEL_FLIP>;
+    constexpr int NT = 64 * N::WPG;
+    constexpr int CS = N::CS;
+    constexpr int NE = 4 * CS;                 // boundary sites of a cell
+    constexpr int NW = NE / 32;                // tagged words per cell
+    constexpr int NWS = (CS + 31) / 32;        // words holding one side
+    static_assert(NE % 64 == 0, "cells of at least 16 sites per side");
+    __shared__ __attribute__((aligned(16))) uint8_t lds[N::LDS];
+    __shared__ uint32_t ring[4 * NWS];         // polled words, per neighbour
+    __shared__ int lastow[4];                  // last outer window of each outer colour, -1: none
+    __shared__ int bad;
+    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    const int cell = (int)xcd_order(blockIdx.x, gridDim.x);
+    const int I = cell % a.NCX, J = cell / a.NCX;
+    const int x0 = I * CS, y0 = J * CS;
+    auto outer_colour = [&](int i, int j) { return a.k_outer == 2 ? (i + j) % 2 : (i % 2) + 2 * (j % 2); };
+    const int my = outer_colour(I, J);
+    // neighbours above, below, left, right; the side of theirs that faces us
+    const int nI[4] = {I, I, I == 0 ? a.NCX - 1 : I - 1, I + 1 == a.NCX ? 0 : I + 1};
+    const int nJ[4] = {J == 0 ? a.NCY - 1 : J - 1, J + 1 == a.NCY ? 0 : J + 1, J, J};
+    uint8_t* tile = lds;
+    double* tab = reinterpret_cast<double*>(lds + N::TILE + wid * N::WAVE);
+    for (int i = lane; i < C::NTAB; i += 64)
+        tab[i] = a.table[i];
+    if (tid < 4)
+        lastow[tid] = -1;
+    if (tid == 0)
+        bad = 0;
+    nest_rows<P, N::TS, CS, true>(tile, a.lat, a.Lx, a.Ly, x0, y0, 0, CS, tid, NT);
+    __syncthreads();
+
+    // boundary site e (0 <= e < NE) of this cell in the tile
+    auto edge_site = [&](int e) -> int {
+        const int side = e / CS, pos = e % CS;
+        const int y = side == 0 ? 0 : side == 1 ? CS - 1 : pos;
+        const int x = side == 2 ? 0 : side == 3 ? CS - 1 : pos;
+        return (y + 1) * N::TS + P + x;
+    };
+    auto publish = [&](uint32_t tag) {
+        for (int k = wid; k < NE / 64; k += N::WPG) {
+            const uint64_t bits = __ballot(tile[edge_site(64 * k + lane)] != 0);
+            if (lane < 2)
+                coh_store(a.edge + (size_t)cell * NW + 2 * k + lane,
+                          (unsigned long long)tag | ((unsigned long long)(uint32_t)(bits >> (32 * lane)) << 32));
+        }
+    };
+    publish((uint32_t)a.ow0);
+
+    uint32_t mine = 0;
+    for (int k = a.ow0; k < a.ow1; ++k) {
+        const int wa = a.ofirst[k] > a.w0 ? a.ofirst[k] : a.w0;
+        const int wb = a.ofirst[k + 1] < a.w1 ? a.ofirst[k + 1] : a.w1;
+        const int co = (int)a.win_colour[wa] / KI;
+        if (co == my) {
+            // wave 0: lanes q*NWS + i poll word i of neighbour q's facing side
+            if (wid == 0 && lane < 4 * NWS) {
+                const int q = lane / NWS, i = lane % NWS;
+                const int face = q == 0 ? 1 : q == 1 ? 0 : q == 2 ? 3 : 2;
+                const int nc = nJ[q] * a.NCX + nI[q];
+                const int last = lastow[outer_colour(nI[q], nJ[q])];
+                const uint32_t want = last >= 0 ? (uint32_t)last + 1u : (uint32_t)a.ow0;
+                const unsigned long long* src = a.edge + (size_t)nc * NW + (face * CS) / 32 + i;
+                unsigned long long v = coh_load(src);
+                if ((uint32_t)v != want) {
+                    const uint64_t t0 = wall_clock64();
+                    for (uint32_t n = 1;; ++n) {
+                        __builtin_amdgcn_s_sleep(1);
+                        v = coh_load(src);
+                        if ((uint32_t)v == want)
+                            break;
+                        if ((n & 7u) == 0) {
+                            if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                                bad = 1;
+                                break;
+                            }
+                            if (wall_clock64() - t0 > a.wait_ticks) {
+                                __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                bad = 1;
+                                break;
+                            }
+                        }
+                    }
+                }
+                ring[lane] = (uint32_t)(v >> 32);
+            }
+            __syncthreads();
+            if (bad)
+                return; // uniform over the workgroup; nothing is written back
+            // the ring from the polled words
+            for (int r = tid; r < NE; r += NT) {
+                const int q = r / CS, pos = r % CS;
+                const int face = q == 0 ? 1 : q == 1 ? 0 : q == 2 ? 3 : 2;
+                const int bit = face * CS + pos;
+                const uint32_t v = (ring[q * NWS + (bit / 32 - (face * CS) / 32)] >> (bit % 32)) & 1u;
+                const int y = q == 0 ? -1 : q == 1 ? CS : pos;
+                const int x = q == 2 ? -1 : q == 3 ? CS : pos;
+                tile[(y + 1) * N::TS + P + x] = (uint8_t)v;
+            }
+            __syncthreads();
+            for (int w = wa; w < wb; ++w) {
+                const int ci = (int)a.win_colour[w] % KI;
+                int lx, ly;
+                nest_slot<CC, KI>(ci, wid, lx, ly);
+                const int m = (J * CC + ly) * a.NBX + I * CC + lx;
+                uint8_t* sub = tile + ly * B * N::TS + lx * B;
+                const uint32_t e = ssa_window<P, B, B, MODEL_FLIP, N::TS>(sub, tab, a.table, (uint32_t)m, (uint32_t)w,
+                                                                          a.win_dur[w], a.k0, a.k1);
+                if (lane == 0) {
+                    a.cnt[m].W = e;
+                    if (e > 0) {
+                        atomicAdd(&a.cnt[m].writes, 1u);
+                        atomicAdd(&a.cnt[m].events, (unsigned long long)e);
+                    }
+                }
+                mine |= e;
+                __syncthreads();
+            }
+            publish((uint32_t)k + 1u);
+        }
+        if (tid == 0)
+            lastow[co] = k;
+        __syncthreads();
+    }
+    (void)mine;
+    nest_rows<P, N::TS, CS, false>(tile, a.lat, a.Lx, a.Ly, x0, y0, 0, CS, tid, NT);
+}
+
 // ---------------------------------------------------------------------------
 // Block ranges of the next resident launch from the workload of the previous
 // one (Sec. 5: the cumulative distribution of the workload histogram mapped
@@ -1963,6 +2107,44 @@ static hipError_t nested_p(int P, const NestedArgs& a, hipStream_t s, LaunchTimi
     case 16: return launch(k_sweep_nested<16, 32, MODEL, CC, KI>, dim3(a.n_cells), dim3(T), s, tm, a);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <int CC, int KI>
+static hipError_t nested_resident_p(int P, const NestedResArgs& a, hipStream_t s, LaunchTiming tm)
+{
+    constexpr int T = 64 * (CC * CC / KI);
+    const void* kern = nullptr;
+    switch (P) {
+    case 1: kern = reinterpret_cast<const void*>(k_sweep_nested_resident<1, 8, CC, KI>); break;
+    case 4: kern = reinterpret_cast<const void*>(k_sweep_nested_resident<4, 16, CC, KI>); break;
+    case 16: kern = reinterpret_cast<const void*>(k_sweep_nested_resident<16, 32, CC, KI>); break;
+    default: return hipErrorInvalidValue;
+    }
+    const unsigned cells = (unsigned)(a.NCX * a.NCY);
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, T, 0) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        (unsigned)(per_cu * cus) < cells)
+        return hipErrorInvalidConfiguration;
+    NestedResArgs args = a;
+    void* pa[] = {&args};
+    if (tm.start)
+        (void)hipEventRecord(tm.start, s);
+    const hipError_t e = hipLaunchCooperativeKernel(kern, dim3(cells), dim3(T), pa, 0, s);
+    if (tm.stop)
+        (void)hipEventRecord(tm.stop, s);
+    return e;
+}
+
+hipError_t launch_sweep_nested_resident(int P, int c, int k_inner, const NestedResArgs& a, hipStream_t s,
+                                        LaunchTiming tm)
+{
+    if (!nested_supported(MODEL_FLIP, P, c, k_inner) || a.w1 <= a.w0 || a.ow1 <= a.ow0)
+        return hipErrorInvalidValue;
+    if (c == 2)
+        return nested_resident_p<2, 2>(P, a, s, tm);
+    return k_inner == 2 ? nested_resident_p<4, 2>(P, a, s, tm) : nested_resident_p<4, 4>(P, a, s, tm);
 }
 
 bool nested_supported(int model, int P, int c, int k_inner)

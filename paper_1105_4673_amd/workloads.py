@@ -19,7 +19,7 @@ def c1(J=1.0, dt=0.1, split=0, T=100.0):
                 params=(1.0, 1.0, J, 0.0, 1.0), b=16, n_colours=2, dt=dt, T=T, split=split, init="bernoulli")
 
 
-def nested(c=4, dtau=0.05, T=20.0, dt=0.1, J=1.0):
+def nested(c=2, dtau=0.05, T=20.0, dt=0.1, J=1.0):
     """The 1024^2 spin-flip lattice on a nested decomposition: coarse cells of
     c x c blocks of 16x16, 2 outer x 2 inner colours, outer Lie dt, inner Lie
     dtau, from Bernoulli(1/2)."""

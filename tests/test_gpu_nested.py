@@ -56,7 +56,10 @@ CASES = {
                            "bernoulli"),
     "flip1024-b16-c4-full-size": ("flip", 1024, (1.0, 1.0, 1.0, 0.0, 1.0), 16, 4, 2, 2, LIE, LIE, 0.1, 0.05, 0.3,
                                   "bernoulli"),
+    "flip1024-b16-c2-full-size": ("flip", 1024, (1.0, 1.0, 1.5, 0.0, 1.0), 16, 2, 2, 2, STRANG, LIE, 0.2, 0.05,
+                                  0.4, "bernoulli"),
 }
+FLIP_CASES = sorted(k for k in CASES if k.startswith("flip"))
 
 
 def _run_case(F, orc, ctx, name, kernel_on, cx=None):
@@ -122,12 +125,18 @@ def test_nested_rectangular_cells_use_flat_sweeps(F, orc, ctx):
     _run_case(F, orc, ctx, "flip256-b16-c4-lie-lie", 1, cx=2)
 
 
-def test_nested_persistent_setting_does_not_apply(F, orc, ctx):
+@pytest.mark.parametrize("resident", [1, 0], ids=["resident", "per-outer-window"])
+def test_nested_persistent_setting_outer_window_calls(F, orc, ctx, resident):
+    """With the persistent setting a spin-flip nested sim advanced one outer
+    window per call runs resident launches (resident knob on) or one launch
+    per outer window (off); both give the oracle's bits at every call."""
     F.fskmc_ctx_set_persistent(ctx, 50)
+    F.fskmc_ctx_set_resident(ctx, resident)
     try:
         _run_case(F, orc, ctx, "flip256-b8-c2-strang-strang", 1)
     finally:
         F.fskmc_ctx_set_persistent(ctx, 0)
+        F.fskmc_ctx_set_resident(ctx, 1)
 
 
 def test_nested_invalid(F, ctx):
@@ -158,3 +167,63 @@ def test_nested_invalid(F, ctx):
     with pytest.raises(E) as ei:  # pair events with 2 inner colours
         make(kind="zgb", prm=(0.5, 1000.0, 10.0), outer_colours=4, inner_colours=2)
     assert ei.value.code == F.FSKMC_EDECOMP
+
+
+@pytest.mark.parametrize("name", FLIP_CASES)
+@pytest.mark.parametrize("persist", [100000, 7], ids=["whole-run", "7-windows-per-launch"])
+def test_nested_resident_matches_oracle(F, orc, ctx, name, persist):
+    """Spin-flip nested sims with persistent launches: every coarse cell is a
+    workgroup resident for the whole launch, cells exchange tagged boundary
+    words between outer windows.  Advanced 11 windows per call, so launches
+    also start and end inside outer windows; the final lattice, the events and
+    W of the last window's active blocks equal the oracle's."""
+    kind, L, prm, b, c, ko, ki, osp, isp, dt, dtau, T, init = CASES[name]
+    F.fskmc_ctx_set_persistent(ctx, persist)
+    F.fskmc_ctx_set_resident(ctx, 1)
+    try:
+        sim = F.Sim(ctx, kind, L, L, prm, bx=b, by=b, dt=dt, T=T, split=osp, seed=1, replica=9,
+                    nested=dict(cx=c, cy=c, outer_colours=ko, inner_colours=ki, inner_split=isp, dtau=dtau))
+        model = _model(orc, kind, L, prm)
+        cmap = nested.nested_colour_map(L, L, b, b, c, c, ko, ki)
+        cols, durs, ends = nested.nested_schedule(osp, ko, isp, ki, dt, dtau, T)
+        if init == "bernoulli":
+            sim.init(1, 0.5)
+            lat = orc.init_bernoulli(L * L, 0.5, 1, 9)
+        else:
+            sim.init(0)
+            lat = np.zeros(L * L, np.uint8)
+        res = orc.fs_run(model, lat, b, b, cmap, ko * ki, cols, durs, 1, 9, want_W=True)
+        while sim.windows()[1] < sim.windows()[0]:
+            sim.advance(min(11, sim.windows()[0] - sim.windows()[1]))
+        F.fskmc_sync(ctx)
+        got = sim.lattice()
+        assert np.array_equal(got, res["lattice"]), int((got != res["lattice"]).sum())
+        assert sim.observe()["events"] == res["events"] > 0
+        active = cmap == cols[-1]
+        np.testing.assert_array_equal(sim.block_events()[active], res["W"][-1][active])
+        sim.close()
+    finally:
+        F.fskmc_ctx_set_persistent(ctx, 0)
+
+
+def test_nested_resident_wait_timeout_reports_edevice(F, orc, ctx):
+    """A wait limit of one clock tick makes the cells' bounded waits give up:
+    the launch aborts, the next synchronising call reports FSKMC_EDEVICE, and
+    a fresh sim on the same context then matches the oracle again."""
+    F.fskmc_ctx_set_persistent(ctx, 100000)
+    F.fskmc_ctx_set_resident(ctx, 1)
+    try:
+        sim = F.Sim(ctx, "flip", 256, 256, (1.0, 1.0, 1.0, 0.0, 1.0), bx=16, by=16, dt=0.2, T=4.0, split=LIE,
+                    nested=dict(cx=2, cy=2, outer_colours=2, inner_colours=2, inner_split=LIE, dtau=0.1))
+        sim.init(1, 0.5)
+        F.fskmc_ctx_set_wait_limit(ctx, 1e-8)
+        sim.run_to_end()
+        with pytest.raises(F.FskmcError) as ei:
+            F.fskmc_sync(ctx)
+        assert ei.value.code == F.FSKMC_EDEVICE
+        F.fskmc_ctx_set_wait_limit(ctx, 2.0)
+        sim.close()
+    finally:
+        F.fskmc_ctx_set_wait_limit(ctx, 2.0)
+        F.fskmc_ctx_set_persistent(ctx, 0)
+    _run_case(F, orc, ctx, "flip256-b8-c2-strang-strang", 1)
