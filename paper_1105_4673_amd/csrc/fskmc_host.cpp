@@ -152,6 +152,7 @@ struct fskmc_sim {
     // grouped by outer colour; per window, one past the last window of its
     // outer window
     bool nested = false, nest_kernel_ok = false;
+    bool nest_resident_fits = true; // cleared when the cells cannot all be resident at once
     int cx = 0, cy = 0, NCX = 0, NCY = 0, k_outer = 0, k_inner = 0, inner_split = 0;
     double dtau = 0.0;
     std::vector<int32_t> cells, cell_off;
@@ -1387,7 +1388,7 @@ int fskmc_sim_advance(fskmc_sim* S, uint64_t n_windows)
     if (S->nested && S->nest_kernel_ok && S->ctx->nested_kernel) {
         const uint64_t end = S->window + n_windows;
         fskmc_ctx* c = S->ctx;
-        const bool resident = c->persist > 0 && c->resident && S->model == FSKMC_MODEL_FLIP;
+        bool resident = c->persist > 0 && c->resident && S->model == FSKMC_MODEL_FLIP && S->nest_resident_fits;
         while (S->window < end) {
             if (resident) {
                 const uint64_t w1 = std::min<uint64_t>(end, S->window + (uint64_t)c->persist);
@@ -1398,6 +1399,7 @@ int fskmc_sim_advance(fskmc_sim* S, uint64_t n_windows)
                 }
                 if (rc != 1)
                     return rc;
+                S->nest_resident_fits = resident = false;
             }
             const uint64_t w1 = std::min<uint64_t>(end, S->outer_end[S->window]);
             if (int rc = enqueue_nested(S, S->window, w1))
