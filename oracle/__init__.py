@@ -36,10 +36,13 @@ GCC_FLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-f
              "-fexcess-precision=standard", "-Wall"]
 
 
-def build(force=True, out=None, defines=()):
-    """Compile the oracle's C part with gcc (test infrastructure)."""
+def build(force=True, out=None, defines=(), extra_flags=()):
+    """Compile the oracle's C part with gcc (test infrastructure).  `out`,
+    `defines` and `extra_flags` build a variant (a planted mistake, a
+    sanitized build) at another path."""
     if out is not None:
-        subprocess.check_call(["gcc"] + GCC_FLAGS + ["-D" + d for d in defines] + ["-o", out, _SRC, "-lm"])
+        subprocess.check_call(["gcc"] + GCC_FLAGS + list(extra_flags) + ["-D" + d for d in defines] +
+                              ["-o", out, _SRC, "-lm"])
         return out
     if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
         return _LIB

@@ -16,17 +16,20 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp
          "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
 
 
-def build(verbose=False):
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + SOURCES
+def build(verbose=False, out=None, extra_flags=()):
+    """Build libfskmc.so in-tree, or a variant at `out` with `extra_flags`
+    (e.g. host-side sanitizers, each after -Xarch_host)."""
+    target = out or LIB
+    tmp = target + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + FLAGS + list(extra_flags) + ["-o", tmp] + SOURCES
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError("hipcc failed building libfskmc")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, target)
+    return target
 
 
 if __name__ == "__main__":

@@ -10,7 +10,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfskmc.so")
+# FSKMC_LIB: another build of the same library (tests load a sanitized one)
+LIB_PATH = os.environ.get("FSKMC_LIB") or os.path.join(_HERE, "libfskmc.so")
 
 FSKMC_OK, FSKMC_EINVAL, FSKMC_ENOMEM, FSKMC_EDEVICE, FSKMC_EDECOMP, FSKMC_EBUSY, FSKMC_ESTATE = 0, -1, -2, -3, -4, -5, -6
 FSKMC_MODEL_FLIP, FSKMC_MODEL_ZGB, FSKMC_MODEL_KAWASAKI = 1, 2, 3
