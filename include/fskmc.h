@@ -125,7 +125,8 @@ typedef struct {
 } fskmc_nested;
 
 /* Schedule: window length dt and final time T (Sec. 2.2, T = n dt; T/dt must
- * be an integer to 1e-9 relative, else FSKMC_EINVAL). */
+ * be an integer to 1e-9 relative, and the run at most 2^31 - 2 windows, else
+ * FSKMC_EINVAL). */
 typedef struct {
     double dt, T;
     int split; /* fskmc_split */

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -279,10 +280,13 @@ int scheme_windows(int split, int K, double dt, double T, fskmc_key key, uint64_
         return fail(FSKMC_EINVAL, "T / dt = %.17g is not an integer", T / dt);
     if (split != FSKMC_LIE && split != FSKMC_STRANG && split != FSKMC_RANDOM)
         return fail(FSKMC_EINVAL, "unknown splitting %d", split);
-    const int64_t steps = (int64_t)nd;
+    // window indices, epochs and the per-colour next-window tables are 32-bit
+    // signed on the device
+    const int64_t max_windows = INT32_MAX - 1;
     const int per = split == FSKMC_STRANG ? 2 * K - 1 : K;
-    if ((int64_t)w0 + steps * per > ((int64_t)1 << 32) - 1)
-        return fail(FSKMC_EINVAL, "more than 2^32 windows");
+    if (nd > (double)max_windows || (int64_t)w0 + (int64_t)nd * per > max_windows)
+        return fail(FSKMC_EINVAL, "more than %lld windows", (long long)max_windows);
+    const int64_t steps = (int64_t)nd;
     const double half = 0.5 * dt;
     col.reserve(col.size() + (size_t)(steps * per));
     dur.reserve(dur.size() + (size_t)(steps * per));

@@ -277,6 +277,9 @@ def test_edge_invalid_inputs(F, ctx):
     assert ei.value.code == F.FSKMC_EDECOMP
     with pytest.raises(E):  # T/dt not an integer
         F.Sim(ctx, FLIP, 64, 64, (1, 1, 1, 0, 1), b=8, dt=0.3, T=1.0)
+    with pytest.raises(E) as ei:  # 3e9 windows: beyond the device's 32-bit window indices, rejected before allocating
+        F.Sim(ctx, FLIP, 64, 64, (1, 1, 1, 0, 1), b=8, dt=1e-9, T=3.0)
+    assert ei.value.code == F.FSKMC_EINVAL
     with pytest.raises(E):  # unsupported block
         F.Sim(ctx, FLIP, 60, 60, (1, 1, 1, 0, 1), b=12, dt=0.1, T=1.0)
     with pytest.raises(E):  # odd number of blocks breaks the 2-colour checkerboard

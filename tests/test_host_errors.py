@@ -50,3 +50,4 @@ def test_context_without_a_device(F):
     with pytest.raises(F.FskmcError) as ei:
         F.fskmc_ctx_create(0)
     assert ei.value.code == F.FSKMC_EDEVICE
+
