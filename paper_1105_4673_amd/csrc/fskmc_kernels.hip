@@ -413,8 +413,13 @@ __device__ __forceinline__ void finish_tree(Tree<P>& T)
 // Leaves from the LDS tile: the table entry of each site's neighbourhood
 // (spin flip: s*(z+1) + #occupied neighbours; reaction model: the pattern
 // s + 3E + 9W + 27N + 81S).
+// qmask (wave-uniform): bit q set = recompute leaf q of every lane; the
+// other leaves keep their values.  The inner sums are always rebuilt, in the
+// same order, so the tree equals a full rebuild whenever the skipped leaves
+// are unchanged.
 template <int P, int BX, int BY, int MODEL, int TS = BX + 2 * P>
-__device__ __forceinline__ void build_tree(const uint8_t* tile, int tb, const double* tab, Tree<P>& T)
+__device__ __forceinline__ void build_tree(const uint8_t* tile, int tb, const double* tab, Tree<P>& T,
+                                           uint32_t qmask = ~0u)
 {
     using C = Cfg<P, BX, BY, MODEL>;
     const Seg<P> o = load_seg<P>(tile + tb);
@@ -426,6 +431,8 @@ __device__ __forceinline__ void build_tree(const uint8_t* tile, int tb, const do
     }
 #pragma unroll
     for (int q = 0; q < P; ++q) {
+        if (!((qmask >> q) & 1u))
+            continue;
         const uint32_t s = byte_at<P>(o, q);
         const uint32_t E = (q + 1 < P) ? byte_at<P>(o, q + 1) : rgt;
         const uint32_t W = (q > 0) ? byte_at<P>(o, q - 1) : lft;
@@ -694,7 +701,22 @@ __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const
                 }
             }
             wave_sync();
-            build_tree<P, BX, BY, MODEL, TS>(tile, tb, tab, T);
+            // only leaves whose neighbourhood holds a changed site can change:
+            // the columns around the event site and its partner; a lane holds
+            // columns c0 .. c0+P-1 with c0 a multiple of P, so these are the
+            // leaves q = column mod P of every lane
+            int xa = lx, xb = lx;
+            if (pick > 0) {
+                const int d = (pick - 1) & 3;
+                xa = d == 1 ? lx - 1 : lx;
+                xb = d == 0 ? lx + 1 : lx;
+            }
+            xa = xa > 0 ? xa - 1 : 0;
+            xb = xb < BX - 1 ? xb + 1 : BX - 1;
+            uint32_t qmask = 0;
+            for (int x = xa; x <= xb; ++x)
+                qmask |= 1u << (x % P);
+            build_tree<P, BX, BY, MODEL, TS>(tile, tb, tab, T, qmask);
         }
         ++e;
         if (e == 0xFFFFFFFFu)
