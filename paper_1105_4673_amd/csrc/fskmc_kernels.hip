@@ -667,18 +667,32 @@ __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const
             const uint32_t s = tile[ts];
             const uint32_t nE = tile[ts + 1], nW = tile[ts - 1], nN = tile[ts + TS], nS = tile[ts - TS];
             const int pat = __builtin_amdgcn_readfirstlane((int)(s + 3 * nE + 9 * nW + 27 * nN + 81 * nS));
-            const double* ch = chan + pat * 14;
+            // the pattern's 13 channel rates through the scalar cache, all
+            // issued before the first is used: the row address is the same in
+            // every lane, so it is made uniform and read in the constant
+            // address space (the table is read-only while kernels run); then
+            // the serial pick: the first non-zero channel with the residual
+            // below its rate, the residual reduced by each channel passed
+            const uint64_t ca = (uint64_t)(uintptr_t)(chan + pat * 14);
+            const uint64_t cu = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(ca >> 32)) << 32) |
+                                (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)ca);
+            const __attribute__((address_space(4))) double* cp =
+                (const __attribute__((address_space(4))) double*)(uintptr_t)cu;
+            double rc[13];
+#pragma unroll
+            for (int c = 0; c < 13; ++c)
+                rc[c] = cp[c];
             int pick = -1, last = -1;
+#pragma unroll
             for (int c = 0; c < 13; ++c) {
-                const double rc = ch[c];
-                if (rc == 0.0)
+                if (rc[c] == 0.0)
                     continue;
                 last = c;
-                if (tg < rc) {
+                if (tg < rc[c]) {
                     pick = c;
                     break;
                 }
-                tg = tg - rc;
+                tg = tg - rc[c];
             }
             if (pick < 0)
                 pick = last;
