@@ -459,63 +459,99 @@ struct FlipSites {
     uint32_t s[(P + 3) / 4], n[(P + 3) / 4];
 };
 
-template <int P, int BX, int BY, int S = BX + 2 * P>
-__device__ __forceinline__ void flip_sites_from_tile(const uint8_t* tile, int tb, FlipSites<P>& F)
+// A lane's segment, the segments above and below it and the sites left and
+// right of it: everything its sites' neighbour counts depend on.
+template <int P>
+struct FlipRows {
+    Seg<P> o, up, dn;
+    uint32_t lft, rgt;
+};
+
+template <int P, int BY, int S>
+__device__ __forceinline__ FlipRows<P> flip_rows_from_tile(const uint8_t* tile, int tb)
+{
+    FlipRows<P> g;
+    g.o = load_seg<P>(tile + tb);
+    g.lft = tile[tb - 1];
+    g.rgt = tile[tb + P];
+    if constexpr (BY > 1) {
+        g.up = load_seg<P>(tile + tb + S);
+        g.dn = load_seg<P>(tile + tb - S);
+    }
+    return g;
+}
+
+template <int P, int BY>
+__device__ __forceinline__ void flip_sites_from_rows(const FlipRows<P>& g, FlipSites<P>& F)
 {
     constexpr int W = (P + 3) / 4;
-    const Seg<P> o = load_seg<P>(tile + tb);
-    const uint32_t lft = tile[tb - 1], rgt = tile[tb + P];
-    Seg<P> up, dn;
-    if constexpr (BY > 1) {
-        up = load_seg<P>(tile + tb + S);
-        dn = load_seg<P>(tile + tb - S);
-    }
 #pragma unroll
     for (int k = 0; k < W; ++k) {
         uint32_t Lw, Rw; // bytes of the -x and +x neighbours of each site
         if constexpr (P == 1) {
-            Lw = lft;
-            Rw = rgt;
+            Lw = g.lft;
+            Rw = g.rgt;
         } else {
-            Lw = (o.w[k] << 8) | (k > 0 ? o.w[k - 1] >> 24 : lft);
-            Rw = (o.w[k] >> 8) | ((k + 1 < W ? (o.w[k + 1] & 0xffu) : rgt) << 24);
+            Lw = (g.o.w[k] << 8) | (k > 0 ? g.o.w[k - 1] >> 24 : g.lft);
+            Rw = (g.o.w[k] >> 8) | ((k + 1 < W ? (g.o.w[k + 1] & 0xffu) : g.rgt) << 24);
         }
         uint32_t n = Lw + Rw;
         if constexpr (BY > 1)
-            n += up.w[k] + dn.w[k];
-        F.s[k] = o.w[k];
+            n += g.up.w[k] + g.dn.w[k];
+        F.s[k] = g.o.w[k];
         F.n[k] = n; // each byte <= 4: no carries between bytes
     }
 }
 
+template <int P, int BX, int BY, int S = BX + 2 * P>
+__device__ __forceinline__ void flip_sites_from_tile(const uint8_t* tile, int tb, FlipSites<P>& F)
+{
+    flip_sites_from_rows<P, BY>(flip_rows_from_tile<P, BY, S>(tile, tb), F);
+}
+
 // Flip of block site (xi, yi) (uniform) to state v: toggle it and add +-1 to
 // the counts of its in-block neighbours.  Site g of the block lives in lane
-// g / P, byte g % P (row-major, P consecutive sites per lane), so each
-// affected byte is one lane compare against a scalar site index.
-template <int P>
-__device__ __forceinline__ uint32_t site_byte(int lane, int g, int k)
+// g / P, byte g % P (row-major, P consecutive sites per lane).  Each lane
+// finds its own bytes from the bit offset o = 8 (g - lane P) of site g from
+// its first site: the site is held here iff 0 <= o < 8P, in word o >> 5 at
+// bit o & 31.  Per site that is a few vector operations on the lane's own
+// offset, instead of a scalar division and compare chain per site and word.
+template <int P, int W>
+__device__ __forceinline__ void site_bits(int o, uint32_t (&m)[W])
 {
-    // bit 0 of site g's byte if g (>= 0) is held in word k of this lane
-    const int q = g % P; // position within the lane's P sites
-    const bool mine = g >= 0 && (q >> 2) == k && lane == g / P;
-    return mine ? 1u << (8 * (q & 3)) : 0u;
+    const bool in = (uint32_t)o < (uint32_t)(8 * P);
+    const uint32_t bit = 1u << (o & 31);
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+        m[k] |= (in && (W == 1 || (o >> 5) == k)) ? bit : 0u;
 }
 
 template <int P, int BX, int BY>
 __device__ __forceinline__ void flip_apply(FlipSites<P>& F, int lane, int xi, int yi, bool v)
 {
     constexpr int W = (P + 3) / 4;
-    const int f = yi * BX + xi;
-    const int nl = xi > 0 ? f - 1 : -1;
-    const int nr = xi < BX - 1 ? f + 1 : -1;
-    const int nu = (BY > 1 && yi > 0) ? f - BX : -1;
-    const int nd = (BY > 1 && yi < BY - 1) ? f + BX : -1;
+    constexpr int FAR = 1 << 24; // moves a neighbour outside the block out of every lane's range
+    const int o = 8 * (yi * BX + xi) - 8 * P * lane;
+    const int dl = xi > 0 ? -8 : FAR;
+    const int dr = xi < BX - 1 ? 8 : FAR;
+    const int du = (BY > 1 && yi > 0) ? -8 * BX : FAR;
+    const int dd = (BY > 1 && yi < BY - 1) ? 8 * BX : FAR;
+    uint32_t own[W], nm[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+        own[k] = nm[k] = 0u;
+    site_bits<P, W>(o, own);
+    site_bits<P, W>(o + dl, nm);
+    site_bits<P, W>(o + dr, nm);
+    site_bits<P, W>(o + du, nm);
+    site_bits<P, W>(o + dd, nm);
+    // counts + nm, or - nm as + (~nm + 1); no byte carries or borrows: a
+    // count stays within 0..4
+    const uint32_t flip = v ? 0u : ~0u, one = v ? 0u : 1u;
 #pragma unroll
     for (int k = 0; k < W; ++k) {
-        F.s[k] ^= site_byte<P>(lane, f, k);
-        const uint32_t nm =
-            site_byte<P>(lane, nl, k) | site_byte<P>(lane, nr, k) | site_byte<P>(lane, nu, k) | site_byte<P>(lane, nd, k);
-        F.n[k] = v ? F.n[k] + nm : F.n[k] - nm;
+        F.s[k] ^= own[k];
+        F.n[k] = F.n[k] + (nm[k] ^ flip) + one;
     }
 }
 
@@ -585,13 +621,6 @@ __device__ __forceinline__ int descend(const Tree<P>& T, double tg, int lane, do
     }
 }
 
-// The serial SSA kernel of one block for one window (Sec. 1, eqs. totalrate
-// and skeleton) on the block's LDS tile.  Draw e uses Philox counter
-// (e, m, w, 0); the draw whose time passes the window end is discarded.
-// Spin flip keeps the block in registers during the window and puts it back
-// into the tile at the end; pair events update the tile in place.
-// Returns the number of accepted events.  With `pre`, (nl0, v0) are this
-// lane's -log U and V of draw e = lane, computed by the caller ahead of time.
 // Draws e0 .. e0+63 of block m in window w, one per lane: (-log U, V).  Not
 // inlined: the event loop then keeps none of the generator's and the
 // logarithm's constants live (they pushed the kernel arguments out of the
@@ -602,13 +631,22 @@ __device__ __noinline__ double2 draw_batch(uint32_t e0, uint32_t m, uint32_t w, 
     return make_double2(-fs_log(unif_open0(rr)), unif_open1(rr));
 }
 
+// The serial SSA kernel of one block for one window (Sec. 1, eqs. totalrate
+// and skeleton) on the block's LDS tile.  Draw e uses Philox counter
+// (e, m, w, 0); the draw whose time passes the window end is discarded.
+// Spin flip keeps the block in registers during the window and puts it back
+// into the tile at the end; pair events update the tile in place.
+// Returns the number of accepted events.  With `pre`, (nl0, v0) are this
+// lane's -log U and V of draw e = lane, computed by the caller ahead of time.
+// With `fin` (spin flip), the lane's site states and neighbour counts come
+// from the caller instead of the tile's block and halo.
 // TS: row stride of the tile (the block's own tile by default; a larger
 // shared tile when several waves hold the sub-blocks of one coarse cell, in
 // which case `tile` points at the sub-block's origin minus one row and P columns).
 template <int P, int BX, int BY, int MODEL, int TS = BX + 2 * P>
 __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const double* __restrict__ chan, uint32_t m,
                                                uint32_t w, double dur, uint32_t k0, uint32_t k1, bool pre = false,
-                                               double nl0 = 0.0, double v0 = 0.0)
+                                               double nl0 = 0.0, double v0 = 0.0, const FlipSites<P>* fin = nullptr)
 {
     using C = Cfg<P, BX, BY, MODEL>;
     const int lane = threadIdx.x & 63;
@@ -617,7 +655,10 @@ __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const
     Tree<P> T;
     FlipSites<P> F;
     if constexpr (MODEL == MODEL_FLIP) {
-        flip_sites_from_tile<P, BX, BY, TS>(tile, tb, F);
+        if (fin)
+            F = *fin;
+        else
+            flip_sites_from_tile<P, BX, BY, TS>(tile, tb, F);
         flip_leaves<P, C::Z>(F, tab, T);
     } else {
         build_tree<P, BX, BY, MODEL, TS>(tile, tb, tab, T);
@@ -1052,18 +1093,11 @@ __device__ __forceinline__ Seg<P> bits_seg(uint32_t b)
     return s;
 }
 
-// Bits r*LPR + off (r = 0..BY-1) of a ballot, packed into bits r.
-template <int LPR, int BY>
-__device__ __forceinline__ uint32_t ballot_column(uint64_t bal, int off)
-{
-    uint32_t out = 0;
-#pragma unroll
-    for (int r = 0; r < BY; ++r)
-        out |= (uint32_t)((bal >> (r * LPR + off)) & 1u) << r;
-    return out;
-}
-
 // Publish the four boundary layers of the block in `tile` with tag `tag`.
+// Rows: each lane puts its P bits at its column; an OR over the lanes of the
+// row (quad DPP when a row is 2 or 4 lanes) leaves the row's bits in all of
+// them.  Columns: lane i < BY fetches the masks of the first and last lane of
+// row i (ds_bpermute), so one ballot per column gives its bits in order.
 template <int P, int BX, int BY>
 __device__ __forceinline__ void publish_edges(const uint8_t* tile, int tb, unsigned long long* edge, uint32_t* ledge,
                                               uint32_t tag, int lane, int r, int c0)
@@ -1072,16 +1106,26 @@ __device__ __forceinline__ void publish_edges(const uint8_t* tile, int tb, unsig
     const uint32_t mask = seg_bits<P>(load_seg<P>(tile + tb));
     uint32_t e0 = 0, e1 = 0;
     if constexpr (C::DIM == 2) {
+        if constexpr (C::LPR == 2 || C::LPR == 4) {
+            uint32_t v = mask << c0;
+            v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false); // quad_perm [1,0,3,2]
+            if constexpr (C::LPR == 4)
+                v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false); // quad_perm [2,3,0,1]
+            e0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+            e1 = (uint32_t)__builtin_amdgcn_readlane((int)v, (BY - 1) * C::LPR);
+        } else {
 #pragma unroll
-        for (int j = 0; j < C::LPR; ++j) {
-            e0 |= (uint32_t)__builtin_amdgcn_readlane((int)mask, j) << (j * P);
-            e1 |= (uint32_t)__builtin_amdgcn_readlane((int)mask, (BY - 1) * C::LPR + j) << (j * P);
+            for (int j = 0; j < C::LPR; ++j) {
+                e0 |= (uint32_t)__builtin_amdgcn_readlane((int)mask, j) << (j * P);
+                e1 |= (uint32_t)__builtin_amdgcn_readlane((int)mask, (BY - 1) * C::LPR + j) << (j * P);
+            }
         }
     }
-    const uint64_t bl = __ballot(c0 == 0 && (mask & 1u));
-    const uint64_t br = __ballot(c0 + P == BX && ((mask >> (P - 1)) & 1u));
-    const uint32_t e2 = ballot_column<C::LPR, BY>(bl, 0);
-    const uint32_t e3 = ballot_column<C::LPR, BY>(br, C::LPR - 1);
+    const int first = (lane % BY) * C::LPR;
+    const uint32_t lm = (uint32_t)__builtin_amdgcn_ds_bpermute(4 * first, (int)mask);
+    const uint32_t rm = (uint32_t)__builtin_amdgcn_ds_bpermute(4 * (first + C::LPR - 1), (int)mask);
+    const uint32_t e2 = (uint32_t)__ballot(lane < BY && (lm & 1u));
+    const uint32_t e3 = (uint32_t)__ballot(lane < BY && ((rm >> (P - 1)) & 1u));
     if (lane < 4) {
         const uint32_t bits = lane == 0 ? e0 : lane == 1 ? e1 : lane == 2 ? e2 : e3;
         coh_store(edge + lane, (unsigned long long)tag | ((unsigned long long)bits << 32));
@@ -1182,10 +1226,15 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
                     want = last >= 0 ? (uint32_t)last + 1u : (uint32_t)a.w0;
                 }
             }
-            // this lane's first draw of the window, computed while the poll is in flight
+            // this lane's first draw of the window and the block's own rows,
+            // taken while the poll is in flight (the empty asm keeps the
+            // compiler from sinking them below the wait); the halo cells read
+            // here are replaced by the neighbours' edges after the wait
             const uint4 rr = philox10(make_uint4((uint32_t)lane, (uint32_t)m, (uint32_t)w, 0u), a.k0, a.k1);
             const double nl0 = -fs_log(unif_open0(rr));
             const double v0 = unif_open1(rr);
+            FlipRows<P> g = flip_rows_from_tile<P, BY, C::S>(tile, tb);
+            asm volatile("" ::"v"(nl0), "v"(v0), "v"(g.o.w[0]), "v"(g.lft), "v"(g.rgt));
             bool bad = false;
             if (active && nb >= 0 && (uint32_t)v != want) {
                 const uint64_t t0 = wall_clock64();
@@ -1216,18 +1265,19 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
             const uint32_t rgt = (uint32_t)__builtin_amdgcn_readlane((int)hv, 3);
             if constexpr (C::DIM == 2) {
                 if (r == 0)
-                    store_seg<P>(tile + tb - C::S, bits_seg<P>(top >> c0));
+                    g.dn = bits_seg<P>(top >> c0);
                 if (r == BY - 1)
-                    store_seg<P>(tile + tb + C::S, bits_seg<P>(bot >> c0));
+                    g.up = bits_seg<P>(bot >> c0);
             }
             if (c0 == 0)
-                tile[tb - 1] = (uint8_t)((lft >> r) & 1u);
+                g.lft = (lft >> r) & 1u;
             if (c0 + P == BX)
-                tile[tb + P] = (uint8_t)((rgt >> r) & 1u);
-            wave_sync();
+                g.rgt = (rgt >> r) & 1u;
+            FlipSites<P> F;
+            flip_sites_from_rows<P, BY>(g, F);
 
             const uint32_t e = ssa_window<P, BX, BY, MODEL_FLIP>(tile, tab, a.table, (uint32_t)m, (uint32_t)w,
-                                                                 a.win_dur[w], a.k0, a.k1, true, nl0, v0);
+                                                                 a.win_dur[w], a.k0, a.k1, true, nl0, v0, &F);
             publish_edges<P, BX, BY>(tile, tb, a.edge + 4 * (size_t)m, ledge + 4 * i, (uint32_t)w + 1u, lane, r, c0);
             if (lane == 0) {
                 a.cnt[m].W = e;
