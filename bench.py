@@ -265,7 +265,7 @@ def cpu_baseline(wl, seconds):
                       f"single-threaded, {events} events in {el:.1f} s CPU"}
 
 
-def bench_batched(F, ctx, n_jobs, stride, chunk=50, wpg=0, k=-1, sequential=True):
+def bench_batched(F, ctx, n_jobs, stride, chunk=50, wpg=0, k=-1, sequential=True, block_edge=0):
     """512 (n_jobs) Ising replicas in one packed launch per window vs the same
     replicas advanced one at a time; every job's final lattice compared."""
     import hashlib
@@ -285,8 +285,12 @@ def bench_batched(F, ctx, n_jobs, stride, chunk=50, wpg=0, k=-1, sequential=True
         init_sim(s, j)
         return s
 
-    edges, edge_rates = autotune.tune_block_edges(ctx, jobs, make_b)
-    log(f"autotune block edge per size: {edges}")
+    if block_edge:
+        edges = {(j["Lx"], j["Ly"]): block_edge for j in jobs}
+        edge_rates = {"chosen": f"all-b{block_edge} (fixed)", "assignments": None, "per_class": None}
+    else:
+        edges, edge_rates = autotune.tune_block_edges(ctx, jobs, make_b)
+    log(f"block edge per size: {edges}")
     jobs = [dict(j, b=edges[(j["Lx"], j["Ly"])]) for j in jobs]
     if wpg:
         best, timings = wpg, None
@@ -357,8 +361,8 @@ def bench_batched(F, ctx, n_jobs, stride, chunk=50, wpg=0, k=-1, sequential=True
             "bit_identical_to_sequential": identical,
             "block_edge_by_size": {f"{k[0]}x{k[1]}": v for k, v in edges.items()},
             "autotune_block_edge": {"chosen": edge_rates["chosen"], "assignments_events_per_s": edge_rates["assignments"],
-                                    "per_class_events_per_s": {f"{k[0]}x{k[1]}": r
-                                                               for k, r in edge_rates["per_class"].items()}},
+                                    "per_class_events_per_s": None if edge_rates["per_class"] is None else
+                                    {f"{k[0]}x{k[1]}": r for k, r in edge_rates["per_class"].items()}},
             "waves_per_group": best, "autotune_s_per_window": timings, "windows_per_launch": best_k,
             "autotune_windows_per_launch_s_per_window": timings_k, "roofline": rl}
 
@@ -521,6 +525,8 @@ def main():
                     help="windows per batched launch (0: one packed launch per window; -1: autotuned)")
     ap.add_argument("--batched-sequential", type=int, default=1,
                     help="0 skips the sequential comparison of the batched measurement")
+    ap.add_argument("--batched-block-edge", type=int, default=0,
+                    help="block edge of every batched job (0: autotuned per lattice size)")
     ap.add_argument("--nested-T", type=float, default=20.0, help="0 skips the nested measurement")
     ap.add_argument("--nested-dtau", type=float, default=0.05)
     ap.add_argument("--nested-cell", type=int, default=2)
@@ -605,7 +611,8 @@ def main():
         F.fskmc_ctx_set_waves_per_group(ctx, args.waves_per_group)
         result["batched"] = bench_batched(F, ctx, args.batched_jobs, args.timing_stride, wpg=args.batched_wpg,
                                           k=args.batched_windows_per_launch,
-                                          sequential=bool(args.batched_sequential))
+                                          sequential=bool(args.batched_sequential),
+                                          block_edge=args.batched_block_edge)
     if args.served_jobs:
         F.fskmc_ctx_set_waves_per_group(ctx, args.waves_per_group)
         result["served"] = bench_served(F, ctx, [float(r) for r in args.served_rates.split(",")], args.served_jobs,
