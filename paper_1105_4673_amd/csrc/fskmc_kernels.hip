@@ -569,12 +569,20 @@ __device__ __forceinline__ void flip_leaves(const FlipSites<P>& F, const double*
     finish_tree(T);
 }
 
+// Launches of at most this many blocks (two waves per SIMD) take the
+// latency-bound variant of the 16-sites-per-lane descent (its own kernels).
+constexpr int kLanePathBlocks = 2048;
+
 // Descent of the heap tree with target tg in [0, R): at each node go left
 // when tg < left or the right subtree is empty, else subtract left and go
 // right.  Returns the leaf index within the block; *tg_out = residual target.
-// xfer: 16 doubles of this wave's LDS, used when P == 16.
+// P == 16 has two ways through the last four levels, the same path and bits:
+// lane_path (every lane descends its own in-lane subtree, no memory; shorter
+// latency, more instructions: for launches with few waves per SIMD) or
+// through xfer, 16 doubles of this wave's LDS (for full launches).
 template <int P>
-__device__ __forceinline__ int descend(const Tree<P>& T, double tg, int lane, double* tg_out, double* xfer)
+__device__ __forceinline__ int descend(const Tree<P>& T, double tg, int lane, double* tg_out, double* xfer,
+                                       bool lane_path)
 {
     // six levels down to the lane, every lane on its own path
     uint64_t ok = ~0ull;
@@ -597,22 +605,60 @@ __device__ __forceinline__ int descend(const Tree<P>& T, double tg, int lane, do
     }
     const int js = (__ffsll((unsigned long long)ok) - 1) & 63;
     if constexpr (P == 16) {
-        // the lane's 16 leaves go to lanes 0..15 through LDS, which rebuild
-        // the four in-lane levels with the same row butterfly and descend
-        const double tu = readlane_f64(tl, js);
-        if (lane == js) {
+        if (!lane_path) {
+            // lane js's 16 leaves go to lanes 0..15 through LDS, which rebuild
+            // the four in-lane levels with the same row butterfly and descend:
+            // fewer instructions, two LDS round trips
+            const double tu = readlane_f64(tl, js);
+            if (lane == js) {
 #pragma unroll
-            for (int i = 0; i < 16; ++i)
-                xfer[i] = T.lv[16 + i];
+                for (int i = 0; i < 16; ++i)
+                    xfer[i] = T.lv[16 + i];
+            }
+            wave_sync();
+            double L2[4], R2[4];
+            row_tree(xfer[lane & 15], L2, R2);
+            uint64_t ok2 = 0xFFFFull; // lanes 0..15 hold the 16 leaves
+            const double t2 = row_descend(L2, R2, tu, lane, ok2);
+            q = (__ffsll((unsigned long long)ok2) - 1) & 15;
+            *tg_out = readlane_f64(t2, q);
+            wave_sync();
+            return js * P + q;
         }
-        wave_sync();
-        double L2[4], R2[4];
-        row_tree(xfer[lane & 15], L2, R2);
-        uint64_t ok2 = 0xFFFFull; // lanes 0..15 hold the 16 leaves
-        const double t2 = row_descend(L2, R2, tu, lane, ok2);
-        q = (__ffsll((unsigned long long)ok2) - 1) & 15;
-        *tg_out = readlane_f64(t2, q);
-        wave_sync();
+        // four levels inside every lane, on the lane's own residual (only lane
+        // js's result is used), down its in-lane subtree: node k has children
+        // 2k and 2k+1, leaves 16..31.  Nodes 2..7 come from the tree; the two
+        // children of the level-3 node are the sums of its four leaves, added
+        // as the tree adds them, and level 4 reads those leaves.  Children are
+        // chosen with selects on the path bits, so registers are never indexed.
+        const bool g1 = !(tl < T.lv[2] || T.lv[3] == 0.0);
+        if (g1)
+            tl = tl - T.lv[2];
+        const double L2 = g1 ? T.lv[6] : T.lv[4];
+        const double R2 = g1 ? T.lv[7] : T.lv[5];
+        const bool g2 = !(tl < L2 || R2 == 0.0);
+        if (g2)
+            tl = tl - L2;
+        double f[4]; // leaves 16 + 8 g1 + 4 g2 + i
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double lo = g1 ? T.lv[24 + i] : T.lv[16 + i];
+            const double hi = g1 ? T.lv[28 + i] : T.lv[20 + i];
+            f[i] = g2 ? hi : lo;
+        }
+        const double L3 = f[0] + f[1];
+        const double R3 = f[2] + f[3];
+        const bool g3 = !(tl < L3 || R3 == 0.0);
+        if (g3)
+            tl = tl - L3;
+        const double L4 = g3 ? f[2] : f[0];
+        const double R4 = g3 ? f[3] : f[1];
+        const bool g4 = !(tl < L4 || R4 == 0.0);
+        if (g4)
+            tl = tl - L4;
+        q = 8 * (g1 ? 1 : 0) + 4 * (g2 ? 1 : 0) + 2 * (g3 ? 1 : 0) + (g4 ? 1 : 0);
+        q = __builtin_amdgcn_readlane(q, js) & (P - 1);
+        *tg_out = readlane_f64(tl, js);
         return js * P + q;
     } else {
         q = __builtin_amdgcn_readlane(q, js) & (P - 1);
@@ -639,14 +685,16 @@ __device__ __noinline__ double2 draw_batch(uint32_t e0, uint32_t m, uint32_t w, 
 // Returns the number of accepted events.  With `pre`, (nl0, v0) are this
 // lane's -log U and V of draw e = lane, computed by the caller ahead of time.
 // With `fin` (spin flip), the lane's site states and neighbour counts come
-// from the caller instead of the tile's block and halo.
+// from the caller instead of the tile's block and halo.  lane_path: the
+// descent's variant for 16 sites per lane (see descend).
 // TS: row stride of the tile (the block's own tile by default; a larger
 // shared tile when several waves hold the sub-blocks of one coarse cell, in
 // which case `tile` points at the sub-block's origin minus one row and P columns).
 template <int P, int BX, int BY, int MODEL, int TS = BX + 2 * P>
 __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const double* __restrict__ chan, uint32_t m,
                                                uint32_t w, double dur, uint32_t k0, uint32_t k1, bool pre = false,
-                                               double nl0 = 0.0, double v0 = 0.0, const FlipSites<P>* fin = nullptr)
+                                               double nl0 = 0.0, double v0 = 0.0, const FlipSites<P>* fin = nullptr,
+                                               bool lane_path = true)
 {
     using C = Cfg<P, BX, BY, MODEL>;
     const int lane = threadIdx.x & 63;
@@ -690,7 +738,7 @@ __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const
             break;
         t = tn;
         double tg;
-        const int leaf = descend<P>(T, V * R, lane, &tg, tab + C::NTAB);
+        const int leaf = descend<P>(T, V * R, lane, &tg, tab + C::NTAB, lane_path);
         const int lx = leaf % BX, ly = leaf / BX;
         if constexpr (MODEL == MODEL_FLIP) {
             const int js = leaf / P, q = leaf % P;
@@ -796,7 +844,8 @@ __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const
 // COH: lattice accesses coherent across the device (persistent sweep).
 template <int P, int BX, int BY, int MODEL, bool COH = false>
 __device__ __forceinline__ void block_window(uint8_t* __restrict__ lat, const double* __restrict__ table, BlockCount* cnt, int Lx,
-                             int Ly, int m, int NBX, uint32_t k0, uint32_t k1, uint32_t w, double dur, uint8_t* lds)
+                             int Ly, int m, int NBX, uint32_t k0, uint32_t k1, uint32_t w, double dur, uint8_t* lds,
+                             bool lane_path)
 {
     using C = Cfg<P, BX, BY, MODEL>;
     const int lane = threadIdx.x & 63;
@@ -844,7 +893,8 @@ __device__ __forceinline__ void block_window(uint8_t* __restrict__ lat, const do
     }
     wave_sync();
 
-    const uint32_t e = ssa_window<P, BX, BY, MODEL>(tile, tab, table, (uint32_t)m, w, dur, k0, k1);
+    const uint32_t e = ssa_window<P, BX, BY, MODEL>(tile, tab, table, (uint32_t)m, w, dur, k0, k1, false, 0.0, 0.0,
+                                                    nullptr, lane_path);
 
     if (e > 0) {
         gstore_seg<P, COH>(grow + gx, load_seg<P>(tile + tb));
@@ -876,26 +926,41 @@ __device__ __forceinline__ uint32_t xcd_order(uint32_t wg, uint32_t G)
     return (G & 7u) ? wg : (wg & 7u) * (G >> 3) + (wg >> 3);
 }
 
-template <int P, int BX, int BY, int MODEL, int WPG>
-__global__ __launch_bounds__(64 * WPG) void k_sweep_single(SweepArgs a)
+// LANE: the descent's latency-bound variant for 16 sites per lane, compiled as
+// its own kernel (k_sweep_single_lane) so the full-launch kernel keeps its
+// register count and occupancy.
+template <int P, int BX, int BY, int MODEL, int WPG, bool LANE>
+__device__ __forceinline__ void sweep_single_body(const SweepArgs& a, uint8_t* lds)
 {
     using C = Cfg<P, BX, BY, MODEL>;
-    __shared__ __attribute__((aligned(16))) uint8_t lds[WPG * C::LDS];
     const int wid = threadIdx.x >> 6;
     const int item = (int)xcd_order(blockIdx.x, gridDim.x) * WPG + wid;
     if (item >= a.n_blocks)
         return; // the whole wave leaves; waves never synchronise with each other
     block_window<P, BX, BY, MODEL>(a.lat, a.table, a.cnt, a.Lx, a.Ly, a.blocks[item], a.NBX, a.k0, a.k1, a.w,
-                                   a.dur, lds + wid * C::LDS);
+                                   a.dur, lds + wid * C::LDS, LANE);
 }
 
 template <int P, int BX, int BY, int MODEL, int WPG>
-__global__ __launch_bounds__(64 * WPG) void k_sweep_batched(const JobDesc* __restrict__ jobs,
-                                                            const uint32_t* __restrict__ item_job,
-                                                            uint32_t n_items, uint64_t step)
+__global__ __launch_bounds__(64 * WPG) void k_sweep_single(SweepArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t lds[WPG * Cfg<P, BX, BY, MODEL>::LDS];
+    sweep_single_body<P, BX, BY, MODEL, WPG, false>(a, lds);
+}
+
+template <int P, int BX, int BY, int MODEL, int WPG>
+__global__ __launch_bounds__(64 * WPG) void k_sweep_single_lane(SweepArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t lds[WPG * Cfg<P, BX, BY, MODEL>::LDS];
+    sweep_single_body<P, BX, BY, MODEL, WPG, true>(a, lds);
+}
+
+template <int P, int BX, int BY, int MODEL, int WPG, bool LANE>
+__device__ __forceinline__ void sweep_batched_body(const JobDesc* __restrict__ jobs,
+                                                   const uint32_t* __restrict__ item_job, uint32_t n_items,
+                                                   uint64_t step, uint8_t* lds)
 {
     using C = Cfg<P, BX, BY, MODEL>;
-    __shared__ __attribute__((aligned(16))) uint8_t lds[WPG * C::LDS];
     const int wid = threadIdx.x >> 6;
     const uint32_t item = xcd_order(blockIdx.x, gridDim.x) * WPG + wid;
     if (item >= n_items)
@@ -911,7 +976,27 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_batched(const JobDesc* __res
     if (k >= (uint32_t)(end - beg))
         return;
     block_window<P, BX, BY, MODEL>(jd.lat, jd.table, jd.cnt, jd.Lx, jd.Ly, jd.blocks[beg + k], jd.NBX, jd.k0,
-                                   jd.k1, (uint32_t)w, jd.win_dur[w], lds + wid * C::LDS);
+                                   jd.k1, (uint32_t)w, jd.win_dur[w], lds + wid * C::LDS, LANE);
+}
+
+template <int P, int BX, int BY, int MODEL, int WPG>
+__global__ __launch_bounds__(64 * WPG) void k_sweep_batched(const JobDesc* __restrict__ jobs,
+                                                            const uint32_t* __restrict__ item_job,
+                                                            uint32_t n_items, uint64_t step)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t lds[WPG * Cfg<P, BX, BY, MODEL>::LDS];
+    sweep_batched_body<P, BX, BY, MODEL, WPG, false>(jobs, item_job, n_items, step, lds);
+}
+
+// The batched sweep with the descent's latency-bound variant (16 sites per
+// lane, small launches).
+template <int P, int BX, int BY, int MODEL, int WPG>
+__global__ __launch_bounds__(64 * WPG) void k_sweep_batched_lane(const JobDesc* __restrict__ jobs,
+                                                                 const uint32_t* __restrict__ item_job,
+                                                                 uint32_t n_items, uint64_t step)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t lds[WPG * Cfg<P, BX, BY, MODEL>::LDS];
+    sweep_batched_body<P, BX, BY, MODEL, WPG, true>(jobs, item_job, n_items, step, lds);
 }
 
 // Lanes 0..7 wait until each block that can interact with block m has
@@ -975,7 +1060,7 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_persistent(PersistArgs a)
             // epoch store after the lattice stores have completed
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             block_window<P, BX, BY, MODEL, true>(a.lat, a.table, a.cnt, a.Lx, a.Ly, m, a.NBX, a.k0, a.k1,
-                                                 (uint32_t)w, a.win_dur[w], lds + wid * C::LDS);
+                                                 (uint32_t)w, a.win_dur[w], lds + wid * C::LDS, true);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             // a workgroup-scope release does not wait for stores to complete;
             // the epoch must not be published before the block's agent-scope
@@ -1030,7 +1115,7 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_batched_persistent(BatchPers
                 return;
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             block_window<P, BX, BY, MODEL, true>(jd.lat, jd.table, jd.cnt, jd.Lx, jd.Ly, m, jd.NBX, jd.k0, jd.k1,
-                                                 (uint32_t)w, jd.win_dur[w], lds + wid * C::LDS);
+                                                 (uint32_t)w, jd.win_dur[w], lds + wid * C::LDS, false);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             __builtin_amdgcn_s_waitcnt(0x0F70); // lattice stores performed before the epoch
             if (lane == 0) {
@@ -1817,7 +1902,9 @@ static hipError_t sweep_single_dispatch(int P, int shape, const SweepArgs& a, hi
         if (P == 4)
             return launch(k_sweep_single<4, 16, 16, MODEL, WPG>, grid, block, s, tm, a);
         if (P == 16)
-            return launch(k_sweep_single<16, 32, 32, MODEL, WPG>, grid, block, s, tm, a);
+            return a.n_blocks <= kLanePathBlocks
+                       ? launch(k_sweep_single_lane<16, 32, 32, MODEL, WPG>, grid, block, s, tm, a)
+                       : launch(k_sweep_single<16, 32, 32, MODEL, WPG>, grid, block, s, tm, a);
         return hipErrorInvalidValue;
     }
     if constexpr (MODEL != MODEL_FLIP) {
@@ -1828,7 +1915,9 @@ static hipError_t sweep_single_dispatch(int P, int shape, const SweepArgs& a, hi
         if (P == 4)
             return launch(k_sweep_single<4, 256, 1, MODEL, WPG>, grid, block, s, tm, a);
         if (P == 16)
-            return launch(k_sweep_single<16, 1024, 1, MODEL, WPG>, grid, block, s, tm, a);
+            return a.n_blocks <= kLanePathBlocks
+                       ? launch(k_sweep_single_lane<16, 1024, 1, MODEL, WPG>, grid, block, s, tm, a)
+                       : launch(k_sweep_single<16, 1024, 1, MODEL, WPG>, grid, block, s, tm, a);
         return hipErrorInvalidValue;
     }
 }
@@ -1844,7 +1933,11 @@ static hipError_t sweep_batched_dispatch(int P, int shape, const JobDesc* jobs, 
         if (P == 4)
             return launch(k_sweep_batched<4, 16, 16, MODEL, WPG>, grid, block, s, tm, jobs, item_job, n_items, step);
         if (P == 16)
-            return launch(k_sweep_batched<16, 32, 32, MODEL, WPG>, grid, block, s, tm, jobs, item_job, n_items, step);
+            return n_items <= (uint32_t)kLanePathBlocks
+                       ? launch(k_sweep_batched_lane<16, 32, 32, MODEL, WPG>, grid, block, s, tm, jobs, item_job,
+                                n_items, step)
+                       : launch(k_sweep_batched<16, 32, 32, MODEL, WPG>, grid, block, s, tm, jobs, item_job, n_items,
+                                step);
         return hipErrorInvalidValue;
     }
     if constexpr (MODEL != MODEL_FLIP) {
@@ -1855,8 +1948,11 @@ static hipError_t sweep_batched_dispatch(int P, int shape, const JobDesc* jobs, 
         if (P == 4)
             return launch(k_sweep_batched<4, 256, 1, MODEL, WPG>, grid, block, s, tm, jobs, item_job, n_items, step);
         if (P == 16)
-            return launch(k_sweep_batched<16, 1024, 1, MODEL, WPG>, grid, block, s, tm, jobs, item_job, n_items,
-                          step);
+            return n_items <= (uint32_t)kLanePathBlocks
+                       ? launch(k_sweep_batched_lane<16, 1024, 1, MODEL, WPG>, grid, block, s, tm, jobs, item_job,
+                                n_items, step)
+                       : launch(k_sweep_batched<16, 1024, 1, MODEL, WPG>, grid, block, s, tm, jobs, item_job,
+                                n_items, step);
         return hipErrorInvalidValue;
     }
 }
