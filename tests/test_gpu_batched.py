@@ -80,6 +80,26 @@ def test_batch_persistent_equals_alone(F, ctx, K, graphs):
     assert got == want
 
 
+def test_batch_full_and_small_launch_kernels(F, ctx):
+    """16 sites per lane in both launch kernels at once: the spin-flip group
+    holds 2112 blocks per window (the full-launch kernel), the reaction group
+    16 (the small-launch kernel); every sim gets the bits it gets alone."""
+    specs = [dict(kind=FLIP, Lx=2112, Ly=2048, params=(1.0, 1.0, 0.8, -0.2, 1.0), b=32, n_colours=2, dt=0.2, T=1.0,
+                  split=0, seed=0, replica=21),
+             dict(kind=ZGB, Lx=256, Ly=256, params=(0.5, 1000.0, 10.0), b=32, n_colours=4, dt=0.05, T=0.5, split=1,
+                  seed=0, replica=22)]
+    want = _alone(F, ctx, specs)
+    F.fskmc_ctx_set_batch_persistent(ctx, 0)
+    sims = _make(F, ctx, specs)
+    while any(s.windows()[1] < s.windows()[0] for s in sims):
+        F.fskmc_batch_advance(ctx, [s.handle for s in sims], 4)
+    F.fskmc_sync(ctx)
+    got = [_digest(s) for s in sims]
+    for s in sims:
+        s.close()
+    assert got == want
+
+
 @pytest.mark.parametrize("K", [0, 4])
 def test_graph_replays_match_eager(F, ctx, K):
     """Two copies of one batch, one replaying a captured graph and one

@@ -192,6 +192,17 @@ def test_flip_block_sizes(F, orc, ctx, b):
     p.step_compare_each(9)
 
 
+@pytest.mark.parametrize("Lx,Ly,b", [(2112, 2048, 32), (4100 * 1024, 1, 1024)], ids=["2d-32x32", "1d-1024"])
+def test_sixteen_sites_per_lane_full_launch(F, orc, ctx, Lx, Ly, b):
+    """More than 2048 active blocks of 16 sites per lane (2112 and 2050 per
+    colour): launches that big take the full-launch kernel, whose descent hands
+    the chosen lane's leaves over through LDS, not the small-launch kernel the
+    smaller cases take; three windows compared in full."""
+    p = Pair(F, orc, ctx, FLIP, Lx, Ly, (1.0, 1.0, 0.8, -0.2, 1.0), b, 2, 0.2, 5.0, "lie", init="bernoulli", seed=5,
+             replica=b)
+    p.step_compare_each(3)
+
+
 @pytest.mark.parametrize("b", [64, 256, 1024])
 def test_flip_1d_rows(F, orc, ctx, b):
     p = Pair(F, orc, ctx, FLIP, 8 * b, 1, (1.0, 1.0, 1.0, -0.5, 1.0), b, 2, 1.0, 10.0, "lie", init="bernoulli",
