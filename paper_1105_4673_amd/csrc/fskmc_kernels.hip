@@ -720,12 +720,16 @@ __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const
         nl_b = -fs_log(unif_open0(rr));
         v_b = unif_open1(rr);
     }
+    // draws e0 .. e0 + avail - 1 are in hand; the draw counter is 32-bit, so
+    // the last batch stops at e = 2^32 - 1, where the window ends
+    uint32_t avail = 64u;
     for (;;) {
         const double R = uniform_f64(T.R);
-        if (R == 0.0)
-            break;
-        if (e - e0 >= 64u) { // rare: a window with more than 64 events
+        if (e - e0 >= avail) { // rare: a window with more than 64 events
+            if (e == 0xFFFFFFFFu)
+                break;
             e0 = e;
+            avail = 0xFFFFFFFFu - e < 64u ? 0xFFFFFFFFu - e : 64u;
             const double2 d = draw_batch(e0, m, w, k0, k1);
             nl_b = d.x;
             v_b = d.y;
@@ -733,6 +737,8 @@ __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const
         const int k = (int)(e - e0);
         const double nl = readlane_f64(nl_b, k);
         const double V = readlane_f64(v_b, k);
+        // R == 0 (no site can change) gives tn = +inf, or NaN when nl == 0:
+        // either way the window ends here without an event
         const double tn = t + nl / R;
         if (!(tn < dur))
             break;
@@ -822,8 +828,6 @@ __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const
             build_tree<P, BX, BY, MODEL, TS>(tile, tb, tab, T, qmask);
         }
         ++e;
-        if (e == 0xFFFFFFFFu)
-            break; // the draw counter is 32-bit; a window never gets here in practice
     }
     if constexpr (MODEL == MODEL_FLIP) {
         if (e > 0) {
