@@ -686,7 +686,9 @@ __device__ __noinline__ double2 draw_batch(uint32_t e0, uint32_t m, uint32_t w, 
 // lane's -log U and V of draw e = lane, computed by the caller ahead of time.
 // With `fin` (spin flip), the lane's site states and neighbour counts come
 // from the caller instead of the tile's block and halo.  lane_path: the
-// descent's variant for 16 sites per lane (see descend).
+// descent's variant for 16 sites per lane (see descend).  With `fout` (spin
+// flip), the lane's final segment is also returned in registers and the tile
+// store is left to the caller's next wave sync.
 // TS: row stride of the tile (the block's own tile by default; a larger
 // shared tile when several waves hold the sub-blocks of one coarse cell, in
 // which case `tile` points at the sub-block's origin minus one row and P columns).
@@ -694,7 +696,7 @@ template <int P, int BX, int BY, int MODEL, int TS = BX + 2 * P>
 __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const double* __restrict__ chan, uint32_t m,
                                                uint32_t w, double dur, uint32_t k0, uint32_t k1, bool pre = false,
                                                double nl0 = 0.0, double v0 = 0.0, const FlipSites<P>* fin = nullptr,
-                                               bool lane_path = true)
+                                               bool lane_path = true, Seg<P>* fout = nullptr)
 {
     using C = Cfg<P, BX, BY, MODEL>;
     const int lane = threadIdx.x & 63;
@@ -830,14 +832,17 @@ __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const
         ++e;
     }
     if constexpr (MODEL == MODEL_FLIP) {
-        if (e > 0) {
-            Seg<P> o;
+        Seg<P> o;
 #pragma unroll
-            for (int k = 0; k < (P + 3) / 4; ++k)
-                o.w[k] = F.s[k];
+        for (int k = 0; k < (P + 3) / 4; ++k)
+            o.w[k] = F.s[k];
+        if (e > 0) {
             store_seg<P>(tile + tb, o);
-            wave_sync();
+            if (!fout)
+                wave_sync();
         }
+        if (fout)
+            *fout = o;
     }
     return e;
 }
@@ -1187,12 +1192,12 @@ __device__ __forceinline__ Seg<P> bits_seg(uint32_t b)
 // row (quad DPP when a row is 2 or 4 lanes) leaves the row's bits in all of
 // them.  Columns: lane i < BY fetches the masks of the first and last lane of
 // row i (ds_bpermute), so one ballot per column gives its bits in order.
+// mask: the lane's P site states as bits (site c0 + q in bit q).
 template <int P, int BX, int BY>
-__device__ __forceinline__ void publish_edges(const uint8_t* tile, int tb, unsigned long long* edge, uint32_t* ledge,
-                                              uint32_t tag, int lane, int r, int c0)
+__device__ __forceinline__ void publish_edges_bits(uint32_t mask, unsigned long long* edge, uint32_t* ledge,
+                                                   uint32_t tag, int lane, int c0)
 {
     using C = Cfg<P, BX, BY, MODEL_FLIP>;
-    const uint32_t mask = seg_bits<P>(load_seg<P>(tile + tb));
     uint32_t e0 = 0, e1 = 0;
     if constexpr (C::DIM == 2) {
         if constexpr (C::LPR == 2 || C::LPR == 4) {
@@ -1220,6 +1225,13 @@ __device__ __forceinline__ void publish_edges(const uint8_t* tile, int tb, unsig
         coh_store(edge + lane, (unsigned long long)tag | ((unsigned long long)bits << 32));
         ledge[lane] = bits;
     }
+}
+
+template <int P, int BX, int BY>
+__device__ __forceinline__ void publish_edges(const uint8_t* tile, int tb, unsigned long long* edge, uint32_t* ledge,
+                                              uint32_t tag, int lane, int c0)
+{
+    publish_edges_bits<P, BX, BY>(seg_bits<P>(load_seg<P>(tile + tb)), edge, ledge, tag, lane, c0);
 }
 
 template <int P, int BX, int BY, int WPG, int BPW>
@@ -1291,7 +1303,7 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
 #pragma unroll 1
     for (int i = 0; i < nown; ++i)
         publish_edges<P, BX, BY>(wl + i * C::TILE, tb, a.edge + 4 * (size_t)(m0 + i), ledge + 4 * i,
-                                 (uint32_t)a.w0, lane, r, c0);
+                                 (uint32_t)a.w0, lane, c0);
 
 #pragma unroll 1
     for (int w = a.w0; w < a.w1; ++w) {
@@ -1364,10 +1376,15 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
                 g.rgt = (rgt >> r) & 1u;
             FlipSites<P> F;
             flip_sites_from_rows<P, BY>(g, F);
+            Seg<P> fo;
 
             const uint32_t e = ssa_window<P, BX, BY, MODEL_FLIP>(tile, tab, a.table, (uint32_t)m, (uint32_t)w,
-                                                                 a.win_dur[w], a.k0, a.k1, true, nl0, v0, &F);
-            publish_edges<P, BX, BY>(tile, tb, a.edge + 4 * (size_t)m, ledge + 4 * i, (uint32_t)w + 1u, lane, r, c0);
+                                                                 a.win_dur[w], a.k0, a.k1, true, nl0, v0, &F, true,
+                                                                 &fo);
+            // from the final sites in registers: the tile store completes at
+            // the wave sync that ends the window
+            publish_edges_bits<P, BX, BY>(seg_bits<P>(fo), a.edge + 4 * (size_t)m, ledge + 4 * i,
+                                          (uint32_t)w + 1u, lane, c0);
             if (lane == 0) {
                 a.cnt[m].W = e;
                 if (e > 0) {
