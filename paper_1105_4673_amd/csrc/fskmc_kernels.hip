@@ -21,7 +21,9 @@
 //   * the descent runs on all 64 lanes at once: each lane follows the path
 //     of its own lane bits, applies the serial rule with its node's child
 //     sums and stays in a 64-bit ballot mask while every decision agrees; the
-//     single consistent lane finishes the last log2(P) levels in registers;
+//     last log2(P) levels run in registers, every lane on its own subtree,
+//     and the single consistent lane's result is kept (with 16 sites per lane
+//     in full launches that lane's leaves go to 16 lanes through LDS instead);
 //   * the Philox4x32-10 draws and their logarithms are computed 64 at a time,
 //     one per lane, and broadcast with readlane as events consume them.
 //
@@ -1167,23 +1169,33 @@ __global__ void k_epoch_init_batched(const JobDesc* __restrict__ jobs)
 template <int P>
 __device__ __forceinline__ uint32_t seg_bits(const Seg<P>& s)
 {
-    uint32_t b = 0;
+    if constexpr (P == 1) {
+        return s.w[0] & 1u;
+    } else {
+        // bit 0 of byte q moves to bit 24 + q: the product's terms below bit
+        // 24 never share a position, so nothing carries into bits 24..27
+        uint32_t b = 0;
 #pragma unroll
-    for (int q = 0; q < P; ++q)
-        b |= ((s.w[q >> 2] >> (8 * (q & 3))) & 1u) << q;
-    return b;
+        for (int k = 0; k < P / 4; ++k)
+            b |= (((s.w[k] & 0x01010101u) * 0x01020408u) >> 24) << (4 * k);
+        return b;
+    }
 }
 
 template <int P>
 __device__ __forceinline__ Seg<P> bits_seg(uint32_t b)
 {
     Seg<P> s;
+    if constexpr (P == 1) {
+        s.w[0] = b & 1u;
+    } else {
+        // x * (1 + 2^7 + 2^14 + 2^21) holds copies of the 4-bit x at bit
+        // offsets 0, 7, 14 and 21, which do not overlap; bit q of the copy at
+        // 7q lands on bit 8q, the one bit of byte q the mask keeps
 #pragma unroll
-    for (int k = 0; k < (P + 3) / 4; ++k)
-        s.w[k] = 0;
-#pragma unroll
-    for (int q = 0; q < P; ++q)
-        s.w[q >> 2] |= ((b >> q) & 1u) << (8 * (q & 3));
+        for (int k = 0; k < P / 4; ++k)
+            s.w[k] = (((b >> (4 * k)) & 0xFu) * 0x00204081u) & 0x01010101u;
+    }
     return s;
 }
 
