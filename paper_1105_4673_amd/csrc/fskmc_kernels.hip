@@ -1339,15 +1339,16 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
                     want = last >= 0 ? (uint32_t)last + 1u : (uint32_t)a.w0;
                 }
             }
-            // this lane's first draw of the window and the block's own rows,
-            // taken while the poll is in flight (the empty asm keeps the
+            // this lane's first draw of the window, the block's own rows and
+            // the window's length, taken while the poll is in flight (the empty asm keeps the
             // compiler from sinking them below the wait); the halo cells read
             // here are replaced by the neighbours' edges after the wait
             const uint4 rr = philox10(make_uint4((uint32_t)lane, (uint32_t)m, (uint32_t)w, 0u), a.k0, a.k1);
             const double nl0 = -fs_log(unif_open0(rr));
             const double v0 = unif_open1(rr);
             FlipRows<P> g = flip_rows_from_tile<P, BY, C::S>(tile, tb);
-            asm volatile("" ::"v"(nl0), "v"(v0), "v"(g.o.w[0]), "v"(g.lft), "v"(g.rgt));
+            const double dur = a.win_dur[w];
+            asm volatile("" ::"v"(nl0), "v"(v0), "v"(g.o.w[0]), "v"(g.lft), "v"(g.rgt), "v"(dur));
             bool bad = false;
             if (active && nb >= 0 && (uint32_t)v != want) {
                 const uint64_t t0 = wall_clock64();
@@ -1390,9 +1391,8 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
             flip_sites_from_rows<P, BY>(g, F);
             Seg<P> fo;
 
-            const uint32_t e = ssa_window<P, BX, BY, MODEL_FLIP>(tile, tab, a.table, (uint32_t)m, (uint32_t)w,
-                                                                 a.win_dur[w], a.k0, a.k1, true, nl0, v0, &F, true,
-                                                                 &fo);
+            const uint32_t e = ssa_window<P, BX, BY, MODEL_FLIP>(tile, tab, a.table, (uint32_t)m, (uint32_t)w, dur,
+                                                                 a.k0, a.k1, true, nl0, v0, &F, true, &fo);
             // from the final sites in registers: the tile store completes at
             // the wave sync that ends the window
             publish_edges_bits<P, BX, BY>(seg_bits<P>(fo), a.edge + 4 * (size_t)m, ledge + 4 * i,
