@@ -1251,7 +1251,7 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
 {
     using C = Cfg<P, BX, BY, MODEL_FLIP>;
     constexpr int KMAX = 128; // colours tracked per wave (the library allows at most 127)
-    constexpr int WAVE = (BPW * C::TILE + C::NTAB * 8 + C::XFER + 3 * BPW * 16 + KMAX * 4 + 15) / 16 * 16;
+    constexpr int WAVE = (BPW * C::TILE + C::NTAB * 8 + C::XFER + 3 * BPW * 16 + KMAX * 4 + BPW * 16 + 15) / 16 * 16;
     __shared__ __attribute__((aligned(16))) uint8_t lds[WPG * WAVE];
     const int wid = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -1266,6 +1266,12 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
     int32_t* nbl = reinterpret_cast<int32_t*>(ledge + 4 * BPW); // [BPW][4]
     int32_t* ncl = nbl + 4 * BPW;                               // [BPW][4]
     int32_t* lastw = ncl + 4 * BPW;                             // [KMAX]
+    // per owned block, the counter record's updates of this launch, written to
+    // HBM once at its end: W of the block's last window (~0: not run), block-
+    // windows with events, and events.  Written every window they would sit in
+    // front of the next poll: loads and stores share one in-order counter, so
+    // waiting for a poll's value also waits for every earlier store and atomic
+    uint32_t* cwl = reinterpret_cast<uint32_t*>(lastw + KMAX); // [BPW][4]: W, writes, events lo, hi
     const int gw = (int)xcd_order(blockIdx.x, gridDim.x) * WPG + wid;
     const int m0 = a.owner ? a.owner[gw] : gw * a.bpw;
     const int want_own = a.owner ? a.owner[gw + 1] - m0 : a.bpw;
@@ -1311,6 +1317,8 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
     }
     for (int k = lane; k < KMAX; k += 64)
         lastw[k] = -1;
+    if (lane < 4 * BPW)
+        cwl[lane] = (lane & 3) == 0 ? ~0u : 0u;
     wave_sync();
 #pragma unroll 1
     for (int i = 0; i < nown; ++i)
@@ -1398,16 +1406,28 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
             publish_edges_bits<P, BX, BY>(seg_bits<P>(fo), a.edge + 4 * (size_t)m, ledge + 4 * i,
                                           (uint32_t)w + 1u, lane, c0);
             if (lane == 0) {
-                a.cnt[m].W = e;
+                cwl[4 * i] = e;
                 if (e > 0) {
-                    atomicAdd(&a.cnt[m].writes, 1u);
-                    atomicAdd(&a.cnt[m].events, (unsigned long long)e);
+                    cwl[4 * i + 1] += 1u;
+                    unsigned long long* ev = reinterpret_cast<unsigned long long*>(cwl + 4 * i + 2);
+                    *ev += e;
                 }
             }
         }
         if (lane == 0)
             lastw[c] = w;
         wave_sync();
+    }
+    if (lane == 0) {
+        for (int i = 0; i < nown; ++i) {
+            const int m = m0 + i;
+            if (cwl[4 * i] != ~0u)
+                a.cnt[m].W = cwl[4 * i];
+            if (cwl[4 * i + 1] != 0u) {
+                atomicAdd(&a.cnt[m].writes, cwl[4 * i + 1]);
+                atomicAdd(&a.cnt[m].events, *reinterpret_cast<const unsigned long long*>(cwl + 4 * i + 2));
+            }
+        }
     }
 #pragma unroll 1
     for (int i = 0; i < nown; ++i) {
