@@ -1252,7 +1252,10 @@ int sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const vo
     const int64_t N = n_sites(S->lat);
     if ((rc = dev_alloc(&S->d_lat, (size_t)N)) || (rc = dev_alloc(&S->d_table, S->table.size())) ||
         (rc = dev_alloc(&S->d_cnt, S->nb)) || (rc = dev_alloc(&S->d_blocks, S->blocks.size())) ||
-        (rc = dev_alloc(&S->d_coff, S->colour_off.size())) || (rc = dev_alloc(&S->d_wcol, S->n_windows)) ||
+        (rc = dev_alloc(&S->d_coff, S->colour_off.size())) ||
+        // padded to whole dwords: the resident sweep reads a window's colour
+        // with a scalar dword load
+        (rc = dev_alloc(&S->d_wcol, (S->n_windows + 3) & ~(size_t)3)) ||
         (rc = dev_alloc(&S->d_wdur, S->n_windows)) || (rc = dev_alloc(&S->d_bcol, S->nb)) ||
         (rc = dev_alloc(&S->d_next, S->next_part.size())) || (rc = dev_alloc(&S->d_nbr, nbr.size())) ||
         (rc = dev_alloc(&S->d_epoch, S->nb)) ||

@@ -103,7 +103,7 @@ struct ResidentArgs {
     const double* table;
     BlockCount* cnt;
     const int8_t* bcol;         // [n_blocks]: colour of each block
-    const int8_t* win_colour;   // per window
+    const int8_t* win_colour;   // per window, the array padded to whole dwords
     const double* win_dur;      // per window
     unsigned long long* edge;   // [n_blocks][4]: tag | bits << 32 of the first/last row, first/last column
     const int32_t* owner;       // [n_waves+1] block range of each wave, or null: wave g owns g*bpw .. +bpw-1

@@ -1246,6 +1246,22 @@ __device__ __forceinline__ void publish_edges(const uint8_t* tile, int tb, unsig
     publish_edges_bits<P, BX, BY>(seg_bits<P>(load_seg<P>(tile + tb)), edge, ledge, tag, lane, c0);
 }
 
+// Uniform reads of read-only per-window tables through the scalar cache
+// (constant address space): a vector load in the resident window loop makes
+// the next wait on a poll also wait for every earlier store, since loads and
+// stores complete through one in-order counter.  The colour array is padded
+// to whole dwords (scalar loads read dwords).
+__device__ __forceinline__ int window_colour(const int8_t* wc, int w)
+{
+    const uint32_t d = *(const __attribute__((address_space(4))) uint32_t*)(uintptr_t)(wc + (w & ~3));
+    return (int)(int8_t)(d >> (8 * (w & 3)));
+}
+
+__device__ __forceinline__ double window_length(const double* wd, int w)
+{
+    return *(const __attribute__((address_space(4))) double*)(uintptr_t)(wd + w);
+}
+
 template <int P, int BX, int BY, int WPG, int BPW>
 __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
 {
@@ -1327,7 +1343,7 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
 
 #pragma unroll 1
     for (int w = a.w0; w < a.w1; ++w) {
-        const int c = a.win_colour[w];
+        const int c = window_colour(a.win_colour, w);
 #pragma unroll 1
         for (int i = 0; i < nown; ++i) {
             if ((int)((cols >> (8 * i)) & 0xffu) != c)
@@ -1355,7 +1371,7 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
             const double nl0 = -fs_log(unif_open0(rr));
             const double v0 = unif_open1(rr);
             FlipRows<P> g = flip_rows_from_tile<P, BY, C::S>(tile, tb);
-            const double dur = a.win_dur[w];
+            const double dur = window_length(a.win_dur, w);
             asm volatile("" ::"v"(nl0), "v"(v0), "v"(g.o.w[0]), "v"(g.lft), "v"(g.rgt), "v"(dur));
             bool bad = false;
             if (active && nb >= 0 && (uint32_t)v != want) {
