@@ -176,7 +176,7 @@ struct NestedResArgs {
     uint8_t* lat;
     const double* table;
     BlockCount* cnt;
-    const int8_t* win_colour;
+    const int8_t* win_colour;   // per window, the array padded to whole dwords
     const double* win_dur;
     const int32_t* ofirst;    // first window of each outer window, n_outer + 1 entries
     unsigned long long* edge; // cells x (cell side / 8) tagged words

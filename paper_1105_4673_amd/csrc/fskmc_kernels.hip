@@ -1623,6 +1623,12 @@ __global__ __launch_bounds__(64 * (CC * CC / KI)) void k_sweep_nested_resident(N
     __shared__ uint32_t ring[4 * NWS];         // polled words, per neighbour
     __shared__ int lastow[4];                  // last outer window of each outer colour, -1: none
     __shared__ int bad;
+    // per block of the cell, the counter record's updates of this launch,
+    // written to HBM once at its end (W of its last window, ~0: not run;
+    // block-windows with events; events): written every inner window they
+    // would sit in front of each barrier, which waits for every earlier store
+    // and atomic
+    __shared__ __attribute__((aligned(16))) uint32_t ncnt[CC * CC * 4];
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     const int cell = (int)xcd_order(blockIdx.x, gridDim.x);
     const int I = cell % a.NCX, J = cell / a.NCX;
@@ -1640,6 +1646,8 @@ __global__ __launch_bounds__(64 * (CC * CC / KI)) void k_sweep_nested_resident(N
         lastow[tid] = -1;
     if (tid == 0)
         bad = 0;
+    for (int t = tid; t < CC * CC * 4; t += NT)
+        ncnt[t] = (t & 3) == 0 ? ~0u : 0u;
     nest_rows<P, N::TS, CS, true>(tile, a.lat, a.Lx, a.Ly, x0, y0, 0, CS, tid, NT);
     __syncthreads();
 
@@ -1664,7 +1672,7 @@ __global__ __launch_bounds__(64 * (CC * CC / KI)) void k_sweep_nested_resident(N
     for (int k = a.ow0; k < a.ow1; ++k) {
         const int wa = a.ofirst[k] > a.w0 ? a.ofirst[k] : a.w0;
         const int wb = a.ofirst[k + 1] < a.w1 ? a.ofirst[k + 1] : a.w1;
-        const int co = (int)a.win_colour[wa] / KI;
+        const int co = window_colour(a.win_colour, wa) / KI;
         if (co == my) {
             // wave 0: lanes q*NWS + i poll word i of neighbour q's facing side
             if (wid == 0 && lane < 4 * NWS) {
@@ -1712,18 +1720,19 @@ __global__ __launch_bounds__(64 * (CC * CC / KI)) void k_sweep_nested_resident(N
             }
             __syncthreads();
             for (int w = wa; w < wb; ++w) {
-                const int ci = (int)a.win_colour[w] % KI;
+                const int ci = window_colour(a.win_colour, w) % KI;
                 int lx, ly;
                 nest_slot<CC, KI>(ci, wid, lx, ly);
                 const int m = (J * CC + ly) * a.NBX + I * CC + lx;
                 uint8_t* sub = tile + ly * B * N::TS + lx * B;
                 const uint32_t e = ssa_window<P, B, B, MODEL_FLIP, N::TS>(sub, tab, a.table, (uint32_t)m, (uint32_t)w,
-                                                                          a.win_dur[w], a.k0, a.k1);
+                                                                          window_length(a.win_dur, w), a.k0, a.k1);
                 if (lane == 0) {
-                    a.cnt[m].W = e;
+                    uint32_t* r = ncnt + 4 * (ly * CC + lx);
+                    r[0] = e;
                     if (e > 0) {
-                        atomicAdd(&a.cnt[m].writes, 1u);
-                        atomicAdd(&a.cnt[m].events, (unsigned long long)e);
+                        r[1] += 1u;
+                        *reinterpret_cast<unsigned long long*>(r + 2) += e;
                     }
                 }
                 mine |= e;
@@ -1736,6 +1745,17 @@ __global__ __launch_bounds__(64 * (CC * CC / KI)) void k_sweep_nested_resident(N
         __syncthreads();
     }
     (void)mine;
+    __syncthreads();
+    for (int bi = tid; bi < CC * CC; bi += NT) {
+        const uint32_t* r = ncnt + 4 * bi;
+        const int m = (J * CC + bi / CC) * a.NBX + I * CC + bi % CC;
+        if (r[0] != ~0u)
+            a.cnt[m].W = r[0];
+        if (r[1] != 0u) {
+            atomicAdd(&a.cnt[m].writes, r[1]);
+            atomicAdd(&a.cnt[m].events, *reinterpret_cast<const unsigned long long*>(r + 2));
+        }
+    }
     nest_rows<P, N::TS, CS, false>(tile, a.lat, a.Lx, a.Ly, x0, y0, 0, CS, tid, NT);
 }
 
