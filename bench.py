@@ -91,11 +91,13 @@ def run_once(F, sim, wl):
 
 
 def resident_bytes(b, block_windows, sites, launches):
-    """Algorithmic HBM bytes of the resident sweep: each launch reads and
-    writes its lattice of `sites` bytes once; per block-window four 8-byte
-    edge words are read and four written, and the 16-byte counter record is
-    updated (28 bytes moved)."""
-    return launches * 2 * sites + block_windows * (64 + 28)
+    """Algorithmic HBM bytes of the resident sweep on a square lattice of
+    b x b blocks: each launch reads and writes its lattice of `sites` bytes
+    once and updates each block's 16-byte counter record once (28 bytes moved:
+    W written, two counters read and written); per block-window four 8-byte
+    edge words are read and four written."""
+    blocks = sites // (b * b)
+    return launches * (2 * sites + 28 * blocks) + block_windows * 64
 
 
 def lds_bytes(kind, b, block_windows, events, resident=False):
