@@ -1350,18 +1350,19 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
                 continue;
             const int m = m0 + i;
             uint8_t* tile = wl + i * C::TILE;
-            unsigned long long v = 0;
+            // every lane issues the first poll (lanes that poll nothing read
+            // their own block's edge word) and reads an LDS edge slot, so no
+            // divergent branch surrounds the load; the values are joined
+            // after the work below
             uint32_t want = 0;
             const int nb = active ? nbl[4 * i + lane] : -1;
-            const unsigned long long* src = a.edge + 4 * (size_t)(nb < 0 ? 0 : nb) + dd;
-            if (active) {
-                if (nb < 0) {
-                    v = (unsigned long long)ledge[4 * (-1 - nb) + dd] << 32;
-                } else {
-                    v = coh_load(src);
-                    const int last = lastw[ncl[4 * i + lane]];
-                    want = last >= 0 ? (uint32_t)last + 1u : (uint32_t)a.w0;
-                }
+            const bool remote = active && nb >= 0;
+            const unsigned long long* src = a.edge + 4 * (size_t)(nb >= 0 ? nb : m) + (active ? dd : 0);
+            const unsigned long long vg = coh_load(src);
+            const unsigned long long vl = (unsigned long long)ledge[4 * (nb < 0 ? -1 - nb : 0) + (active ? dd : 0)] << 32;
+            if (remote) {
+                const int last = lastw[ncl[4 * i + lane]];
+                want = last >= 0 ? (uint32_t)last + 1u : (uint32_t)a.w0;
             }
             // this lane's first draw of the window, the block's own rows and
             // the window's length, taken while the poll is in flight (the empty asm keeps the
@@ -1373,6 +1374,7 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
             FlipRows<P> g = flip_rows_from_tile<P, BY, C::S>(tile, tb);
             const double dur = window_length(a.win_dur, w);
             asm volatile("" ::"v"(nl0), "v"(v0), "v"(g.o.w[0]), "v"(g.lft), "v"(g.rgt), "v"(dur));
+            unsigned long long v = remote ? vg : (active ? vl : 0ull);
             bool bad = false;
             if (active && nb >= 0 && (uint32_t)v != want) {
                 const uint64_t t0 = wall_clock64();
