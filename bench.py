@@ -2,40 +2,58 @@
 """Benchmark of the fractional-step lattice KMC sweep on one MI355X.
 
 Metric: KMC events per second (accepted lattice updates) on one GPU, at
-bit-exact agreement with the CPU oracle (the parity tests check the same
-kernels and launch configuration).
+bit-exact agreement with the CPU oracle: every leg below whose workload has a
+stored oracle value (tests/golden/full_runs.json, written by the oracle alone)
+compares its run's final lattice hash and event total with it and reports
+`bit_exact_vs_oracle`.
 
 Headline (value): one timed step = one whole run of the 1024^2 Ising-type
 lattice (spin flip, Arrhenius rates, J=1, h=0, beta=1, 16x16 blocks, 2 colours,
 Lie dt=0.1, T=100 = 2000 windows) from a Bernoulli(1/2) start: the init kernel,
 the sweep (by default all 2000 windows in one resident persistent launch:
 blocks stay in LDS, neighbours exchange tagged boundary words) and the final
-observables.  Each step uses its own Philox replica key.  Lattices and tables
-are resident in HBM before the timed region starts.
+observables.  Each step uses its own Philox replica key (warm-up step 0 is
+replica 0, the stored oracle case).  Lattices and tables are resident in HBM
+before the timed region starts.
 
 Also in the JSON line:
-  roofline      the sweep kernel's algorithmic HBM bytes per launch over its
-                average launch duration (kernel-side HIP events on the launch
-                stream, every k-th timed launch), against the 8 TB/s HBM peak;
-  per_window    the same workload with one sweep launch per window;
-  cpu_baseline  the oracle (plain single-threaded C, the blockwise scheme) on
-                a bounded sample of the same workload, on this host;
+  roofline      the headline sweep kernel against its roofline as the method
+                defines it: algorithmic bytes per launch of the staged design
+                (per block-window the block and halo read and the block
+                written, HBM; the staged block, the sum tree's build and per
+                event its descent and dirty paths, LDS) over the average
+                launch duration (kernel-side HIP events on the launch stream),
+                against 8 TB/s and 78.6 TB/s; frac is the larger term and
+                `bound` names it; the resident design's own HBM bytes are a
+                `variant`; `traffic` is the rocprofv3 FETCH/WRITE bytes per
+                launch (copy-calibrated) when recorded for this kernel source;
+  per_window    the headline workload with one sweep launch per window;
+  c0            the 64^2 latency case (8x8 blocks, empty start, T=10): one
+                launch per window and one resident launch;
+  c1_grid       the 18 points of the 1024^2 grid (J in {0.5,1,2}, Lie/Strang,
+                dt in {0.01,0.1,1}), one whole run each, bit-exactness checked;
+  c2            the 4096^2 A/B reaction lattice (4 colours, 32x32 blocks,
+                Strang dt=0.05, T=10, y=0.5, D=10) with one launch per window,
+                its roofline with the pair model's bytes, the other (y, D)
+                points, and the first 280 windows checked bit for bit;
+  cpu_baseline  the oracle (plain single-threaded C, the blockwise scheme), one
+                replica per worker process on all host cores (at most 16) for
+                a bounded time each: per-core and aggregate events/s, cores,
+                nproc and CPU model;
   batched       512 independent Ising replicas of mixed sizes (edges
                 128..1024) advanced together (one packed launch per window or
                 K windows per persistent launch, both autotuned with the waves
                 per workgroup), against the same 512 runs advanced one after
                 another, bit-identity checked;
-  served        Poisson request streams (50, 200, 1000 jobs/s) of mixed Ising
-                and A/B reaction jobs (edges log-uniform in [64, 2048], T in
-                [10, 200]) served with continuous batching: p50/p99
-                time-to-result and aggregate events/s;
-  sweep         events/s of the other (J, dt, split) points of the 1024^2
-                workload (fewer steps);
-  balance       workload rebalancing (Sec. 5) on a half-filled 2048^2
+  served        Poisson request streams (50, 200, 1000 jobs/s, 256 requests
+                each) of mixed Ising and A/B reaction jobs (edges log-uniform
+                in [64, 2048], T in [10, 200]) served with continuous batching:
+                p50/p99 time-to-result, offered and achieved events/s;
+  balance       workload rebalancing (Sec. 6) on a half-filled 2048^2
                 lattice: one launch per window, resident launches on fixed
                 block ranges and on ranges rebalanced from the previous
                 launch's workload histogram, bit-identity checked;
-  nested        the nested decomposition (Sec. 6) of the 1024^2 lattice
+  nested        the nested decomposition (Sec. 5) of the 1024^2 lattice
                 (coarse cells of 2x2 blocks, outer Lie dt=0.1, inner Lie
                 dtau=0.05): one resident launch (a workgroup per coarse cell
                 for the whole run, tagged ring exchange between outer
@@ -44,7 +62,9 @@ Also in the JSON line:
                 window list, bit-identity checked.
 """
 import argparse
+import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -57,64 +77,77 @@ HBM_PEAK_GBS = 8000.0
 LDS_PEAK_GBS = 128 * 256 * 2.4  # 128 B/clk per CU, 256 CUs, 2.4 GHz = 78.6 TB/s
 # VALU issue: 256 CUs x 4 SIMDs x 2.4e9 cycles/s, one wave64 instruction per 4 cycles per SIMD
 VALU_PEAK_GINST = 256 * 4 * 2.4 / 4
+GOLDEN = os.path.join(ROOT, "tests", "golden", "full_runs.json")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def hbm_bytes(kind, b, block_windows, writes):
-    """Algorithmic HBM bytes of the sweep: per block-window the block and its
-    one-site halo are read (b^2 + 4b bytes) and its 16-byte counter record is
-    updated (28 bytes moved: W written, two counters read and written); a block
-    that changed is written back (b^2 bytes; the pair model also writes its
-    halo, b^2 + 4b)."""
+def golden_record(wl, replica, windows=None):
+    """The stored oracle value (sha256, events, name) of a run of workload
+    `wl` with this replica key (the whole run, or its first `windows`
+    windows), or None."""
+    try:
+        with open(GOLDEN) as f:
+            recs = json.load(f)
+    except (OSError, ValueError):
+        return None
+    for name, g in recs.items():
+        p = g["params"]
+        prm = ((p["k_a"], p["k_d"], p["J"], p["h"], p["beta"]) if g["kind"] == "flip" else
+               (p["D"], p["J"], p["beta"]) if g["kind"] == "kawasaki" else (p["y"], p["k_r"], p["D"]))
+        if (g["kind"] == wl["kind"] and (g.get("Lx", g["L"]), g.get("Ly", g["L"])) == (wl["Lx"], wl["Ly"]) and
+                tuple(map(float, prm)) == tuple(map(float, wl["params"])) and g["b"] == wl["b"] and
+                g["n_colours"] == wl["n_colours"] and float(g["dt"]) == float(wl["dt"]) and
+                float(g["T"]) == float(wl["T"]) and g["split"] == wl["split"] and g["init"] == wl["init"] and
+                g["seed"] == wl.get("seed", 0) and g["replica"] == replica and
+                (g.get("whole_run") if windows is None else g["windows"] == windows)):
+            return g["sha256"], g["events"], name
+    return None
+
+
+def check_golden(sim, wl, replica, windows=None):
+    """Compare a finished run with the stored oracle value: True / False, or
+    None when no value is stored for it."""
+    g = golden_record(wl, replica, windows)
+    if g is None:
+        return None, None
+    got = (hashlib.sha256(sim.lattice().tobytes()).hexdigest(), sim.observe()["events"])
+    return got == (g[0], g[1]), g[2]
+
+
+# --- algorithmic bytes of the method (staged design) -------------------------
+def hbm_bytes_staged(kind, b, block_windows):
+    """Per block-window: the block and its one-site halo read (b^2 + 4b
+    bytes), the block written back (b^2; pair events also write the halo,
+    b^2 + 4b) and the 4-byte event count W."""
     rd = b * b + 4 * b
     wr = b * b if kind == "flip" else b * b + 4 * b
-    return block_windows * (rd + 28) + writes * wr
+    return block_windows * (rd + wr + 4)
 
 
-def make_sim(F, ctx, wl, replica=None):
-    return F.Sim(ctx, wl["kind"], wl["Lx"], wl["Ly"], wl["params"], b=wl["b"], n_colours=wl["n_colours"],
-                 dt=wl["dt"], T=wl["T"], split=wl["split"], seed=wl.get("seed", 0),
-                 replica=wl.get("replica", 0) if replica is None else replica)
-
-
-def init_sim(sim, wl):
-    sim.init(1 if wl["init"] == "bernoulli" else 0, 0.5)
-
-
-def run_once(F, sim, wl):
-    init_sim(sim, wl)
-    sim.run_to_end()
-    return sim.observe()
+def lds_bytes(kind, b, block_windows, events):
+    """Per block-window the staged block and halo (b^2 + 4b), the n = b^2
+    leaves written (8n) and the n-1 inner nodes built from two children (24
+    bytes each); per accepted event a descent reading both children on
+    log2 n levels (16 log2 n) and the dirty paths, bounded by 5 leaves (spin
+    flip: the site and its four neighbours) or 8 (pair events) of
+    8 + 24 log2 n bytes each.  The kernels here keep the tree in registers:
+    this is the method's figure, not their traffic."""
+    n = b * b
+    lg = math.log2(n)
+    dirty = 5 if kind == "flip" else 8
+    return block_windows * (n + 4 * b + 8 * n + 24 * (n - 1)) + events * (16 * lg + dirty * (8 + 24 * lg))
 
 
 def resident_bytes(b, block_windows, sites, launches):
-    """Algorithmic HBM bytes of the resident sweep on a square lattice of
-    b x b blocks: each launch reads and writes its lattice of `sites` bytes
-    once and updates each block's 16-byte counter record once (28 bytes moved:
-    W written, two counters read and written); per block-window four 8-byte
-    edge words are read and four written."""
+    """HBM bytes of the resident design (spin flip): each launch reads and
+    writes its lattice of `sites` bytes once and updates each block's 16-byte
+    counter record once (28 bytes moved); per block-window four 8-byte edge
+    words are read and four written."""
     blocks = sites // (b * b)
     return launches * (2 * sites + 28 * blocks) + block_windows * 64
-
-
-def lds_bytes(kind, b, block_windows, events, resident=False):
-    """Algorithmic LDS bytes of the method with the block's sum tree in LDS:
-    per block-window the staged block and halo (the halo only when the
-    blocks stay resident), the leaves written (8n) and the n-1 inner nodes
-    built from two children each (24 bytes); per accepted event a descent
-    reading both children on log2 n levels (16 log2 n) and the dirty paths,
-    bounded by 5 leaves (spin flip: the site and its four neighbours) or 8
-    (pair events) of 8 + 24 log2 n bytes each.  The kernels here keep the
-    tree in registers, so this is the method's figure, not the traffic."""
-    import math
-    n = b * b
-    lg = math.log2(n)
-    stage = 4 * b if resident else n + 4 * b
-    dirty = 5 if kind == "flip" else 8
-    return block_windows * (stage + 8 * n + 24 * (n - 1)) + events * (16 * lg + dirty * (8 + 24 * lg))
 
 
 def nested_bytes(b, c, cells_per_launch, block_windows, launches):
@@ -126,89 +159,119 @@ def nested_bytes(b, c, cells_per_launch, block_windows, launches):
     return launches * cells_per_launch * ((side + 2) ** 2 - 4 + side * side) + block_windows * 28
 
 
-def measured_valu(symbol):
-    """VALU wave-instructions per launch of `symbol` (rocprofv3 SQ_INSTS_VALU,
-    recorded in profiles/valu.json for the workload the bench runs), or None
-    when there is no record or the kernel source has changed since."""
-    import hashlib
+def _counters(symbol):
+    """rocprofv3 counters recorded in profiles/counters.json for `symbol`
+    (only when recorded from the current kernel source), or None."""
     try:
-        with open(os.path.join(ROOT, "profiles", "valu.json")) as f:
-            rec = json.load(f)["kernels"].get(symbol)
+        with open(os.path.join(ROOT, "profiles", "counters.json")) as f:
+            rec = json.load(f)
         with open(os.path.join(ROOT, "paper_1105_4673_amd", "csrc", "fskmc_kernels.hip"), "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
-    except (OSError, ValueError, KeyError):
+    except (OSError, ValueError):
         return None, None
-    if not rec or rec.get("kernel_source_sha256") != sha:
-        return None, None
-    return rec["valu_per_dispatch"], rec["source"]
+    k = rec.get("kernels", {}).get(symbol)
+    if not k or k.get("kernel_source_sha256") != sha:
+        return None, rec
+    return k, rec
 
 
-def measured_traffic(symbol):
-    """HBM bytes per launch of `symbol` from the rocprofv3 FETCH_SIZE /
-    WRITE_SIZE passes recorded in profiles/hbm_traffic.json (scaled by the
-    copy calibration), or None when there is no record or the kernel source
-    has changed since the counters were taken."""
-    import hashlib
-    try:
-        with open(os.path.join(ROOT, "profiles", "hbm_traffic.json")) as f:
-            rec = json.load(f)["kernels"].get(symbol)
-        with open(os.path.join(ROOT, "paper_1105_4673_amd", "csrc", "fskmc_kernels.hip"), "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
-    except (OSError, ValueError, KeyError):
-        return None, None
-    if not rec or rec.get("kernel_source_sha256") != sha:
-        return None, None
-    return rec["traffic_bytes_per_launch"], rec["source"]
+def measured(symbol):
+    """(traffic bytes per launch, VALU per launch, occupancy, LDS bank-conflict
+    share, source) from the recorded counters of this kernel source."""
+    k, rec = _counters(symbol) if symbol else (None, None)
+    if not k:
+        return None, None, None, None, None
+    cal = rec.get("calibration", {})
+    traffic = None
+    if "fetch_kib_per_dispatch" in k and "write_kib_per_dispatch" in k:
+        traffic = 1024 * (k["fetch_kib_per_dispatch"] / cal.get("fetch_factor", 1.0) +
+                          k["write_kib_per_dispatch"] / cal.get("write_factor", 1.0))
+    return traffic, k.get("valu_per_dispatch"), k.get("occupancy_waves_per_simd"), k.get("lds_bank_conflict_share"), \
+        k.get("source")
 
 
-def roofline(F, ctx, kind, b, obs_list, launches, kernel_name, resident_sites=0, symbol=None):
-    """Achieved algorithmic HBM GB/s of the sweep kernel: bytes per launch
-    (from the run's block-window and write-back counts) over the average
-    duration of the launches bracketed by kernel-side timing events."""
+def roofline(F, ctx, kind, b, obs_list, launches, kernel_name, symbol=None, resident_sites=0):
+    """The sweep kernel against the method's roofline: staged-design HBM and
+    LDS bytes per launch over the average duration of the launches bracketed
+    by kernel-side timing events; frac is the larger of the two terms."""
     ms_total, n_timed = F.fskmc_ctx_read_kernel_timing(ctx)
-    bw = sum(o["block_windows"] for o in obs_list)
-    wr = sum(o["writes"] for o in obs_list)
-    if resident_sites:
-        bytes_per_launch = resident_bytes(b, bw, resident_sites, launches) / max(launches, 1)
-    elif isinstance(b, (list, tuple)):  # one block edge per simulation
-        total = sum(hbm_bytes(kind, bb, o["block_windows"], o["writes"]) for bb, o in zip(b, obs_list))
-        bytes_per_launch = total / max(launches, 1)
-    else:
-        bytes_per_launch = hbm_bytes(kind, b, bw, wr) / max(launches, 1)
+    launches = max(launches, 1)
+    bs = b if isinstance(b, (list, tuple)) else [b] * len(obs_list)
+    hbm = sum(hbm_bytes_staged(kind, bb, o["block_windows"]) for bb, o in zip(bs, obs_list)) / launches
+    lds = sum(lds_bytes(kind, bb, o["block_windows"], o["events"]) for bb, o in zip(bs, obs_list)) / launches
     avg = ms_total / 1e3 / max(n_timed, 1)
-    achieved = bytes_per_launch / avg / 1e9 if n_timed else 0.0
-    traffic, source = measured_traffic(symbol)
-    ev = sum(o["events"] for o in obs_list)
-    if isinstance(b, (list, tuple)):
-        lds = sum(lds_bytes(kind, bb, o["block_windows"], o["events"]) for bb, o in zip(b, obs_list))
+    ok = n_timed > 0 and avg > 0
+    hbm_a = hbm / avg / 1e9 if ok else 0.0
+    lds_a = lds / avg / 1e9 if ok else 0.0
+    terms = {"hbm": {"achieved": hbm_a, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_a / HBM_PEAK_GBS,
+                     "bytes_per_launch": hbm},
+             "lds": {"achieved": lds_a, "peak": LDS_PEAK_GBS, "unit": "GB/s", "frac": lds_a / LDS_PEAK_GBS,
+                     "bytes_per_launch": lds}}
+    bound = max(terms, key=lambda t: terms[t]["frac"])
+    traffic, valu, occ, bank, source = measured(symbol)
+    out = {"bound": bound, "achieved": terms[bound]["achieved"], "peak": terms[bound]["peak"], "unit": "GB/s",
+           "frac": terms[bound]["frac"], "traffic": traffic, "kernel": kernel_name, "symbol": symbol,
+           "avg_launch_us": avg * 1e6, "timed_launches": n_timed, "launches": launches,
+           "hbm": terms["hbm"], "lds": terms["lds"], "counters_source": source,
+           "occupancy_waves_per_simd": occ, "lds_bank_conflict_share": bank}
+    if traffic is not None:
+        out["traffic_over_algorithmic_hbm"] = traffic / hbm if hbm else None
+    if resident_sites:
+        rb = sum(resident_bytes(bb, o["block_windows"], resident_sites, 1) for bb, o in zip(bs, obs_list)) / launches
+        out["variant"] = {"design": "resident (blocks stay in LDS, edge words exchanged)",
+                          "hbm_bytes_per_launch": rb, "achieved": rb / avg / 1e9 if ok else 0.0,
+                          "frac": (rb / avg / 1e9 if ok else 0.0) / HBM_PEAK_GBS}
+        if traffic is not None and rb:
+            out["variant"]["traffic_over_algorithmic"] = traffic / rb
+    if valu is not None and ok:
+        out["alu"] = {"bound": "alu", "achieved": valu / avg / 1e9, "peak": VALU_PEAK_GINST, "unit": "Ginst/s",
+                      "frac": valu / avg / 1e9 / VALU_PEAK_GINST, "valu_per_launch": valu}
+    return out
+
+
+# --- single-simulation legs ----------------------------------------------------
+def make_sim(F, ctx, wl, replica=None):
+    return F.Sim(ctx, wl["kind"], wl["Lx"], wl["Ly"], wl["params"], b=wl["b"], n_colours=wl["n_colours"],
+                 dt=wl["dt"], T=wl["T"], split=wl["split"], seed=wl.get("seed", 0),
+                 replica=wl.get("replica", 0) if replica is None else replica)
+
+
+def init_sim(sim, wl):
+    sim.init(1 if wl["init"] == "bernoulli" else 0, 0.5)
+
+
+def run_once(F, sim, wl, windows=None):
+    init_sim(sim, wl)
+    if windows is None:
+        sim.run_to_end()
     else:
-        lds = lds_bytes(kind, b, bw, ev, resident=bool(resident_sites))
-    lds_per_launch = lds / max(launches, 1)
-    lds_achieved = lds_per_launch / avg / 1e9 if n_timed else 0.0
-    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": source, "kernel": kernel_name,
-            "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg * 1e6, "timed_launches": n_timed,
-            "lds": {"bound": "lds", "achieved": lds_achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                    "frac": lds_achieved / LDS_PEAK_GBS, "bytes_per_launch": lds_per_launch},
-            "alu": alu_term(symbol, avg if n_timed else 0.0)}
+        sim.advance(windows)
+    return sim.observe()
 
 
-def alu_term(symbol, avg_s):
-    """Measured VALU issue rate of a launch against the chip's issue peak
-    (recorded SQ_INSTS_VALU per launch over the measured launch duration): a
-    utilisation of the SIMDs, not an algorithmic operation count."""
-    valu, source = measured_valu(symbol) if symbol else (None, None)
-    if valu is None or avg_s <= 0:
-        return None
-    achieved = valu / avg_s / 1e9
-    return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GINST, "unit": "Ginst/s",
-            "frac": achieved / VALU_PEAK_GINST, "valu_per_launch": valu, "valu_source": source}
+def kernel_symbol(wl, persist, resident, wpg):
+    P = wl["b"] ** 2 // 64
+    kind = wl["kind"]
+    if persist > 0 and resident and kind == "flip":
+        cap = 4 if P == 16 else 8  # blocks a resident wave can hold
+        return (f"k_sweep_resident<P={P},{kind}> ({persist} windows per launch)",
+                f"k_sweep_resident<{P}, {wl['b']}, {wl['b']}, {1 if wpg == 1 else 2}, {cap}>")
+    if persist > 0:
+        return f"k_sweep_persistent<P={P},{kind}> ({persist} windows per launch)", None
+    mod = 1 if kind == "flip" else 2
+    return f"k_sweep_single<P={P},{kind}>", f"k_sweep_single<{P}, {wl['b']}, {wl['b']}, {mod}, {wpg}>"
 
 
-def bench_plain(F, ctx, wl, steps, warmup, stride, persist=0, resident=False, wpg=2):
+def bench_plain(F, ctx, wl, steps, warmup, stride, persist=0, resident=False, wpg=2, check=True):
+    """`warmup` untimed and `steps` timed whole runs, replica i for run i;
+    replica 0 (a warm-up run, or an extra untimed run when warmup is 0) is
+    compared with the stored oracle value."""
     sims = [make_sim(F, ctx, wl, replica=i) for i in range(warmup + steps)]
+    exact, golden = None, None
     for i in range(warmup):
         run_once(F, sims[i], wl)
+        if i == 0 and check:
+            exact, golden = check_golden(sims[0], wl, 0)
     F.fskmc_sync(ctx)
     F.fskmc_ctx_read_kernel_timing(ctx)  # discard
     F.fskmc_ctx_set_kernel_timing(ctx, stride)
@@ -217,30 +280,111 @@ def bench_plain(F, ctx, wl, steps, warmup, stride, persist=0, resident=False, wp
     obs = [run_once(F, sims[warmup + i], wl) for i in range(steps)]
     F.fskmc_sync(ctx)
     el = time.perf_counter() - t0
-    P = wl["b"] ** 2 // 64
+    kname, symbol = kernel_symbol(wl, persist, resident, wpg)
     if persist > 0:
         launches = sum(-(-o["window"] // persist) for o in obs)
-        kname = (f"k_sweep_{'resident' if resident else 'persistent'}<P={P},{wl['kind']}> "
-                 f"({persist} windows per launch)")
-        cap = 4 if P == 16 else 8  # blocks a resident wave can hold
-        symbol = f"k_sweep_resident<{P}, {wl['b']}, {wl['b']}, {1 if wpg == 1 else 2}, {cap}>" if resident else None
     else:
         launches = sum(o["window"] for o in obs)
-        kname = f"k_sweep_single<P={P},{wl['kind']}>"
-        symbol = f"k_sweep_single<{P}, {wl['b']}, {wl['b']}, {1 if wl['kind'] == 'flip' else 2}, {wpg}>"
-    rl = roofline(F, ctx, wl["kind"], wl["b"], obs, launches, kname,
-                  resident_sites=wl["Lx"] * wl["Ly"] if resident else 0, symbol=symbol)
+    rl = roofline(F, ctx, wl["kind"], wl["b"], obs, launches, kname, symbol=symbol,
+                  resident_sites=wl["Lx"] * wl["Ly"] if (resident and persist > 0) else 0)
     F.fskmc_ctx_set_kernel_timing(ctx, 0)
+    if warmup == 0 and check:
+        run_once(F, sims[0], wl)
+        exact, golden = check_golden(sims[0], wl, 0)
     for s in sims:
         s.close()
     events = sum(o["events"] for o in obs)
     return {"events": events, "seconds": el, "obs": obs, "roofline": rl,
-            "windows": sum(o["window"] for o in obs)}
+            "windows": sum(o["window"] for o in obs), "bit_exact_vs_oracle": exact, "oracle_case": golden}
 
 
-def cpu_baseline(wl, seconds):
-    """Oracle events/s on a bounded sample: consecutive windows of replica 0
-    from the workload's own initial state, until `seconds` of CPU time."""
+def bench_c0(F, ctx, steps, stride, wpg):
+    """The 64^2 latency case: one launch per window, and the whole run in
+    one resident persistent launch."""
+    from paper_1105_4673_amd import workloads
+    wl = workloads.C0
+    out = {"workload": wl["name"]}
+    for label, persist in (("per_window", 0), ("resident", 100000)):
+        F.fskmc_ctx_set_persistent(ctx, persist)
+        q = bench_plain(F, ctx, wl, steps, 1, stride, persist, True, wpg)
+        out[label] = {"value": q["events"] / q["seconds"], "ms_per_step": q["seconds"] * 1e3 / steps,
+                      "events_per_step": q["events"] / steps, "windows_per_step": q["windows"] // steps,
+                      "us_per_window": q["seconds"] * 1e6 / q["windows"],
+                      "bit_exact_vs_oracle": q["bit_exact_vs_oracle"], "oracle_case": q["oracle_case"],
+                      "kernel": q["roofline"]["kernel"], "avg_launch_us": q["roofline"]["avg_launch_us"]}
+        log(f"c0 {label}: {out[label]['value']:.3g} events/s, {out[label]['us_per_window']:.2f} us per window, "
+            f"bit-exact {q['bit_exact_vs_oracle']}")
+    return out
+
+
+def bench_c1_grid(F, ctx, persist, resident, wpg):
+    """The 18 points of the 1024^2 grid, one whole run (replica 0) each,
+    every run compared with its stored oracle value."""
+    from paper_1105_4673_amd import workloads
+    out = []
+    F.fskmc_ctx_set_persistent(ctx, persist)
+    for J in (0.5, 1.0, 2.0):
+        for split in (0, 1):
+            for dt in (0.01, 0.1, 1.0):
+                wl = workloads.c1(J=J, dt=dt, split=split)
+                s = make_sim(F, ctx, wl, replica=0)
+                F.fskmc_sync(ctx)
+                t0 = time.perf_counter()
+                o = run_once(F, s, wl)
+                F.fskmc_sync(ctx)
+                el = time.perf_counter() - t0
+                exact, case = check_golden(s, wl, 0)
+                s.close()
+                out.append({"workload": wl["name"], "value": o["events"] / el, "ms_per_step": el * 1e3,
+                            "events_per_step": o["events"], "windows": o["window"],
+                            "bit_exact_vs_oracle": exact})
+                log(f"c1 {wl['name']}: {o['events'] / el:.3g} events/s ({el * 1e3:.1f} ms), bit-exact {exact}")
+    return out
+
+
+def bench_c2(F, ctx, steps, stride, wpg, grid=True):
+    """The 4096^2 A/B reaction lattice: whole runs to T=10 with one launch per
+    window (y=0.5, D=10 timed with its roofline; the other (y, D) points one
+    run each), and the first 280 windows of replica 1 against the oracle."""
+    from paper_1105_4673_amd import workloads
+    F.fskmc_ctx_set_persistent(ctx, 0)
+    wl = workloads.c2(y=0.5, D=10.0)
+    chk = make_sim(F, ctx, wl, replica=1)
+    run_once(F, chk, wl, windows=280)
+    exact, case = check_golden(chk, wl, 1, windows=280)
+    chk.close()
+    q = bench_plain(F, ctx, wl, steps, 0, stride, 0, False, wpg, check=False)
+    out = {"workload": wl["name"], "value": q["events"] / q["seconds"], "ms_per_step": q["seconds"] * 1e3 / steps,
+           "events_per_step": q["events"] / steps, "windows_per_step": q["windows"] // steps,
+           "bit_exact_vs_oracle_first_280_windows": exact, "oracle_case": case, "roofline": q["roofline"]}
+    log(f"c2 {wl['name']}: {out['value']:.3g} events/s, bit-exact (280 windows) {exact}, "
+        f"kernel avg {q['roofline']['avg_launch_us']:.2f} us")
+    if grid:
+        pts = []
+        for y in (0.3, 0.5, 0.53):
+            for D in (0.0, 10.0):
+                if (y, D) == (0.5, 10.0):
+                    continue
+                w2 = workloads.c2(y=y, D=D)
+                s = make_sim(F, ctx, w2, replica=0)
+                F.fskmc_sync(ctx)
+                t0 = time.perf_counter()
+                o = run_once(F, s, w2)
+                F.fskmc_sync(ctx)
+                el = time.perf_counter() - t0
+                s.close()
+                pts.append({"workload": w2["name"], "value": o["events"] / el, "ms_per_step": el * 1e3,
+                            "events_per_step": o["events"], "coverage": [c / o["n_sites"] for c in o["count"]]})
+                log(f"c2 {w2['name']}: {o['events'] / el:.3g} events/s")
+        out["grid"] = pts
+    return out
+
+
+# --- CPU baseline: the oracle on the host cores ------------------------------------
+def _oracle_worker(args):
+    """One replica of the workload in the oracle, consecutive windows from its
+    own start until `seconds` of this process's CPU time."""
+    wl, replica, seconds = args
     import numpy as np
     import oracle
     if wl["kind"] == "flip":
@@ -251,20 +395,56 @@ def cpu_baseline(wl, seconds):
         model = oracle.Model("zgb", wl["Lx"], wl["Ly"], y=y, k_r=k_r, D=D)
     b = wl["b"]
     cmap = oracle.colour_map(model, b, b, wl["n_colours"])
-    cols, durs, _ = oracle.schedule(wl["split"], wl["n_colours"], wl["dt"], wl["T"])
-    lat = oracle.init_bernoulli(model.N, 0.5, 0, 0) if wl["init"] == "bernoulli" else np.zeros(model.N, np.uint8)
+    cols, durs, _ = oracle.schedule(wl["split"], wl["n_colours"], wl["dt"], wl["T"], 0, replica)
+    lat = (oracle.init_bernoulli(model.N, 0.5, 0, replica) if wl["init"] == "bernoulli"
+           else np.zeros(model.N, np.uint8))
     t0 = time.process_time()
     w = events = 0
     while w < len(cols) and time.process_time() - t0 < seconds:
         n = min(2, len(cols) - w)
-        res = oracle.fs_run(model, lat, b, b, cmap, wl["n_colours"], cols[w:w + n], durs[w:w + n], 0, 0, w0=w)
+        res = oracle.fs_run(model, lat, b, b, cmap, wl["n_colours"], cols[w:w + n], durs[w:w + n], 0, replica, w0=w)
         lat = res["lattice"]
         events += res["events"]
         w += n
-    el = time.process_time() - t0
-    return {"value": events / el, "unit": "events/s", "cores": 1, "kind": "oracle",
-            "sample": f"{wl['name']}: windows [0,{w}) of {len(cols)} of replica 0 from the same start, "
-                      f"single-threaded, {events} events in {el:.1f} s CPU"}
+    return events, time.process_time() - t0, w
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(wl, seconds, max_workers=16):
+    """The oracle timed on the host cores: one replica per worker process
+    (all cores this process may use, at most `max_workers`), each running
+    consecutive windows of its replica from the workload's start for
+    `seconds` of CPU time.  Must run before the GPU is initialised (the
+    workers are forked)."""
+    import multiprocessing as mp
+    nproc = os.cpu_count()
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = nproc
+    workers = max(1, min(avail, max_workers))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_oracle_worker, [(wl, r, seconds) for r in range(workers)])
+    wall = time.perf_counter() - t0
+    events = sum(r[0] for r in res)
+    per_core = [r[0] / r[1] for r in res if r[1] > 0]
+    return {"value": events / wall, "unit": "events/s", "cores": workers, "kind": "oracle",
+            "per_core": sum(per_core) / len(per_core), "nproc": nproc, "cpu_affinity": avail,
+            "cpu_model": _cpu_model(),
+            "sample": f"{wl['name']}: replicas 0..{workers - 1}, one per worker process, each running consecutive "
+                      f"windows from its own start for {seconds:g} s of CPU time ({sum(r[2] for r in res)} windows, "
+                      f"{events} events in {wall:.1f} s wall); the oracle is single-threaded per replica"}
 
 
 def bench_batched(F, ctx, n_jobs, stride, chunk=50, wpg=0, k=-1, sequential=True, block_edge=0):
@@ -335,7 +515,20 @@ def bench_batched(F, ctx, n_jobs, stride, chunk=50, wpg=0, k=-1, sequential=True
     dig_b = [hashlib.sha256(s.lattice().tobytes()).hexdigest() for s in sims]
     for s in sims:
         s.close()
-    log(f"batched: {ev_b} events in {el:.3f} s")
+    # every job whose whole run has a stored oracle value (tests/golden/c3_jobs.json)
+    stored = {}
+    try:
+        with open(os.path.join(ROOT, "tests", "golden", "c3_jobs.json")) as f:
+            stored = json.load(f)["jobs"]
+    except (OSError, ValueError, KeyError):
+        pass
+    checked = matched = 0
+    for j, d, o in zip(jobs, dig_b, obs):
+        g = stored.get(f"{j['name']}_b{j['b']}")
+        if g is not None:
+            checked += 1
+            matched += (g["sha256"], g["events"]) == (d, o["events"])
+    log(f"batched: {ev_b} events in {el:.3f} s; {matched} of {checked} stored oracle runs matched")
 
     if sequential:
         seq = make_all(jobs)
@@ -361,6 +554,8 @@ def bench_batched(F, ctx, n_jobs, stride, chunk=50, wpg=0, k=-1, sequential=True
             "sequential_value": ev_s / el_s if sequential else None, "sequential_seconds": el_s if sequential else None,
             "speedup_vs_sequential": (ev_b / el) / (ev_s / el_s) if sequential else None,
             "bit_identical_to_sequential": identical,
+            "bit_exact_vs_oracle": (matched == checked) if checked else None,
+            "oracle_jobs_checked": checked, "oracle_jobs_matched": matched,
             "block_edge_by_size": {f"{k[0]}x{k[1]}": v for k, v in edges.items()},
             "autotune_block_edge": {"chosen": edge_rates["chosen"], "assignments_events_per_s": edge_rates["assignments"],
                                     "per_class_events_per_s": None if edge_rates["per_class"] is None else
@@ -370,7 +565,7 @@ def bench_batched(F, ctx, n_jobs, stride, chunk=50, wpg=0, k=-1, sequential=True
 
 
 def bench_balance(F, ctx, windows, chunk):
-    """Workload rebalancing (Sec. 5) on the half-filled 2048^2 lattice: the
+    """Workload rebalancing (Sec. 6) on the half-filled 2048^2 lattice: the
     first `windows` windows with one launch per window, with resident launches
     of `chunk` windows on fixed block ranges, and on ranges rebalanced from the
     previous launch's workload; final lattices compared."""
@@ -411,7 +606,7 @@ def bench_balance(F, ctx, windows, chunk):
 
 
 def bench_nested(F, ctx, T, dtau, c, stride):
-    """Nested decomposition (Sec. 6) of the 1024^2 lattice, whole runs to T:
+    """Nested decomposition (Sec. 5) of the 1024^2 lattice, whole runs to T:
     the nested kernel (one launch per outer window), the flat per-window
     sweep and the flat persistent sweep on the same window list."""
     import hashlib
@@ -456,7 +651,7 @@ def bench_nested(F, ctx, T, dtau, c, stride):
             avg = timing[0] / 1e3 / max(timing[1], 1)
             achieved = per_launch / avg / 1e9
             P = wl["b"] ** 2 // 64
-            traffic, source = measured_traffic(f"k_sweep_nested<{P}, {wl['b']}, 1, {c}, 2>")
+            traffic, _, _, _, source = measured(f"k_sweep_nested<{P}, {wl['b']}, 1, {c}, 2>")
             out[label]["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                       "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                                       "traffic_source": source, "kernel": f"k_sweep_nested<P={P},c={c}>",
@@ -486,10 +681,17 @@ def bench_served(F, ctx, rates, n_jobs, windows_per_step, budget_gib):
         done = srv.run(reqs)
         wall = time.perf_counter() - t0
         s = summarize(done, wall)
+        span = max(r.arrival for r in reqs)
         s.update({"rate_jobs_per_s": rate, "requests": n_jobs, "batched_steps": srv.steps,
-                  "last_arrival_s": max(r.arrival for r in reqs),
-                  "sites_mean": sum(r.spec["Lx"] * r.spec["Ly"] for r in reqs) / n_jobs})
-        log(f"served rate {rate}/s: {s['jobs']} jobs, {s['events']} events in {wall:.2f} s, "
+                  "last_arrival_s": span,
+                  # the event rate the arrival stream asks for (all its jobs' events over the arrival span)
+                  # against what was delivered (the same events over the wall time of the whole run)
+                  "offered_events_per_s": s["events"] / span if span > 0 else None,
+                  "achieved_events_per_s": s["events_per_s"],
+                  "sites_mean": sum(r.spec["Lx"] * r.spec["Ly"] for r in reqs) / n_jobs,
+                  "max_resident": srv.max_resident})
+        log(f"served rate {rate}/s: {s['jobs']} jobs, {s['events']} events in {wall:.2f} s "
+            f"(offered {s['offered_events_per_s']:.3g}, achieved {s['achieved_events_per_s']:.3g} events/s), "
             f"p50 {s['p50_time_to_result_s']:.3f} s p99 {s['p99_time_to_result_s']:.3f} s")
         out.append(s)
     return out
@@ -511,11 +713,15 @@ def main():
                          "launch; 0: one launch per window)")
     ap.add_argument("--no-resident", action="store_true",
                     help="persistent sweeps stream every block from HBM each window instead of keeping it in LDS")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-workers", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--c0-steps", type=int, default=5, help="0 skips the 64^2 latency case")
+    ap.add_argument("--no-c1-grid", action="store_true", help="skip the 18-point 1024^2 grid")
+    ap.add_argument("--c2-steps", type=int, default=1, help="0 skips the 4096^2 reaction lattice")
+    ap.add_argument("--no-c2-grid", action="store_true", help="only the y=0.5, D=10 point of the reaction lattice")
     ap.add_argument("--batched-jobs", type=int, default=512, help="0 skips the batched measurement")
-    ap.add_argument("--sweep", action="store_true", help="also time the other (J, dt, split) points")
-    ap.add_argument("--served-jobs", type=int, default=64, help="requests per arrival rate; 0 skips serving")
+    ap.add_argument("--served-jobs", type=int, default=256, help="requests per arrival rate; 0 skips serving")
     ap.add_argument("--served-rates", default="50,200,1000")
     ap.add_argument("--served-windows-per-step", type=int, default=4)
     ap.add_argument("--balance-windows", type=int, default=200,
@@ -532,6 +738,8 @@ def main():
     ap.add_argument("--nested-T", type=float, default=20.0, help="0 skips the nested measurement")
     ap.add_argument("--nested-dtau", type=float, default=0.05)
     ap.add_argument("--nested-cell", type=int, default=2)
+    ap.add_argument("--only-headline", action="store_true",
+                    help="the headline legs only (no per-window, C0, C1 grid, C2, balance, nested, batched, served)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -539,6 +747,19 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               f"(the fractional-step sweep runs on a single MI355X here)", file=sys.stderr)
         sys.exit(2)
+    if args.only_headline:
+        args.c0_steps = args.c2_steps = args.batched_jobs = args.served_jobs = args.balance_windows = 0
+        args.nested_T = 0.0
+        args.no_c1_grid = True
+
+    from paper_1105_4673_amd import workloads
+    wl = workloads.c1(J=args.J, dt=args.dt, split=args.split)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before the GPU is initialised: the oracle's worker processes are forked
+        log(f"cpu baseline: the oracle on up to {args.cpu_workers} host cores, {args.cpu_seconds:g} s each ...")
+        cpu = cpu_baseline(wl, args.cpu_seconds, args.cpu_workers)
+        log(f"cpu baseline: {cpu['value']:.3g} events/s on {cpu['cores']} cores ({cpu['per_core']:.3g} per core)")
 
     import torch
     if args.copy_probe:
@@ -552,20 +773,18 @@ def main():
         return
 
     from paper_1105_4673_amd import fskmc as F
-    from paper_1105_4673_amd import workloads
 
     torch.cuda.init()
     ctx = F.fskmc_ctx_create(0, torch.cuda.current_stream().cuda_stream)
     F.fskmc_ctx_set_waves_per_group(ctx, args.waves_per_group)
     F.fskmc_ctx_set_persistent(ctx, args.persistent)
     F.fskmc_ctx_set_resident(ctx, not args.no_resident)
-    wl = workloads.c1(J=args.J, dt=args.dt, split=args.split)
     log(f"workload {wl['name']}")
     resident = args.persistent > 0 and not args.no_resident
     p = bench_plain(F, ctx, wl, args.steps, args.warmup, args.timing_stride, args.persistent, resident,
                     args.waves_per_group)
     log(f"plain: {args.steps} steps, {p['events']} events in {p['seconds']:.3f} s, "
-        f"kernel avg {p['roofline']['avg_launch_us']:.2f} us")
+        f"kernel avg {p['roofline']['avg_launch_us']:.2f} us, bit-exact {p['bit_exact_vs_oracle']}")
     result = {
         "metric": METRIC,
         "value": p["events"] / p["seconds"],
@@ -583,26 +802,30 @@ def main():
                    "colours": wl["n_colours"], "windows_per_step": p["windows"] // args.steps,
                    "events_per_step": p["events"] / args.steps, "waves_per_group": args.waves_per_group,
                    "persistent_windows_per_launch": args.persistent, "resident": resident},
+        "bit_exact_vs_oracle": p["bit_exact_vs_oracle"],
+        "oracle_case": p["oracle_case"],
         "roofline": p["roofline"],
     }
-    if args.persistent > 0:
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
+    if args.persistent > 0 and not args.only_headline:
         F.fskmc_ctx_set_persistent(ctx, 0)
         q = bench_plain(F, ctx, wl, min(args.steps, 3), 1, args.timing_stride, 0, wpg=args.waves_per_group)
         F.fskmc_ctx_set_persistent(ctx, args.persistent)
-        result["per_window"] = {"value": q["events"] / q["seconds"], "ms_per_step": q["seconds"] * 1e3 / min(args.steps, 3),
-                                "roofline": q["roofline"]}
-        log(f"one launch per window: {result['per_window']['value']:.3g} events/s")
-    if args.sweep:
-        sweep = []
-        for J in (0.5, 1.0, 2.0):
-            for dt in (0.01, 0.1, 1.0):
-                for split in (0, 1):
-                    w2 = workloads.c1(J=J, dt=dt, split=split)
-                    q = bench_plain(F, ctx, w2, 1, 1, 0, args.persistent, resident, args.waves_per_group)
-                    sweep.append({"workload": w2["name"], "value": q["events"] / q["seconds"],
-                                  "ms_per_step": q["seconds"] * 1e3, "events_per_step": q["events"]})
-                    log(f"sweep {w2['name']}: {q['events'] / q['seconds']:.3g} events/s")
-        result["sweep"] = sweep
+        result["per_window"] = {"value": q["events"] / q["seconds"],
+                                "ms_per_step": q["seconds"] * 1e3 / min(args.steps, 3),
+                                "bit_exact_vs_oracle": q["bit_exact_vs_oracle"], "roofline": q["roofline"]}
+        log(f"one launch per window: {result['per_window']['value']:.3g} events/s, "
+            f"bit-exact {q['bit_exact_vs_oracle']}")
+    if args.c0_steps:
+        result["c0"] = bench_c0(F, ctx, args.c0_steps, args.timing_stride, args.waves_per_group)
+        F.fskmc_ctx_set_persistent(ctx, args.persistent)
+    if not args.no_c1_grid:
+        result["c1_grid"] = bench_c1_grid(F, ctx, args.persistent, resident, args.waves_per_group)
+    if args.c2_steps:
+        result["c2"] = bench_c2(F, ctx, args.c2_steps, args.timing_stride, args.waves_per_group,
+                                grid=not args.no_c2_grid)
+        F.fskmc_ctx_set_persistent(ctx, args.persistent)
     if args.balance_windows:
         result["balance"] = bench_balance(F, ctx, args.balance_windows, args.balance_chunk)
     if args.nested_T:
@@ -615,13 +838,13 @@ def main():
                                           k=args.batched_windows_per_launch,
                                           sequential=bool(args.batched_sequential),
                                           block_edge=args.batched_block_edge)
+        result["batched"]["speedup_vs_plain"] = result["batched"]["value"] / result["value"]
     if args.served_jobs:
         F.fskmc_ctx_set_waves_per_group(ctx, args.waves_per_group)
         result["served"] = bench_served(F, ctx, [float(r) for r in args.served_rates.split(",")], args.served_jobs,
                                         args.served_windows_per_step, budget_gib=64.0)
-    if not args.no_cpu_baseline:
-        log("cpu baseline ...")
-        result["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        for srv in result["served"]:
+            srv["vs_plain"] = srv["achieved_events_per_s"] / result["value"]
     F.fskmc_ctx_destroy(ctx)
     print(json.dumps(result), flush=True)
 

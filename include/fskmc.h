@@ -104,7 +104,7 @@ typedef struct {
     const int* colour_map;
 } fskmc_decomp;
 
-/* Nested (hierarchical) decomposition (Sec. 6, eqs. sublatt2 and opdecomp2).
+/* Nested (hierarchical) decomposition (Sec. 5, eqs. sublatt2 and opdecomp2).
  * Coarse cells of cx x cy fine blocks (bx x by sites each) carry the outer
  * colouring over coarse positions (I, J): 2 colours (I+J)%2, 4 colours
  * (I%2)+2(J%2); inside a cell, fine blocks at (i, j) carry the inner colouring
@@ -157,6 +157,10 @@ typedef struct {
  * hipStream_t (e.g. torch.cuda.current_stream().cuda_stream) used for all
  * work, or NULL for a library-owned stream.  out: receives the handle. */
 int fskmc_ctx_create(int device, void* hip_stream, fskmc_ctx** out);
+/* Wait for the context's stream, then destroy every simulation still created
+ * on the context (their handles become invalid: do not pass them to
+ * fskmc_sim_destroy afterwards) and the context itself.  A borrowed stream is
+ * not destroyed. */
 int fskmc_ctx_destroy(fskmc_ctx* ctx);
 
 /* Message of the last failed call on this thread ("" if none).  The pointer
@@ -208,8 +212,11 @@ int fskmc_sim_init(fskmc_sim* sim, int kind, double p);
 int fskmc_sim_set_lattice(fskmc_sim* sim, const uint8_t* host, size_t n);
 int fskmc_sim_get_lattice(fskmc_sim* sim, uint8_t* host, size_t n);
 
-/* Enqueue the next n_windows windows of the schedule (one kernel launch per
- * window).  FSKMC_ESTATE if that would pass the final time T. */
+/* Enqueue the next n_windows windows of the schedule: one kernel launch per
+ * window by default, up to K windows per persistent launch with
+ * fskmc_ctx_set_persistent(ctx, K > 0), one launch per outer window for
+ * nested sims.  FSKMC_ESTATE if that would pass the final time T, or if a
+ * persistent launch of this sim aborted (see fskmc_ctx_set_wait_limit). */
 int fskmc_sim_advance(fskmc_sim* sim, uint64_t n_windows);
 /* Enqueue all remaining windows. */
 int fskmc_sim_run_to_end(fskmc_sim* sim);
@@ -310,19 +317,22 @@ int fskmc_ctx_set_rebalance(fskmc_ctx* ctx, int on);
  * sims use resident launches (see fskmc_sim_create_nested). */
 int fskmc_ctx_set_nested(fskmc_ctx* ctx, int on);
 
-/* Workload histogram (Sec. 5, eq. wload): out[m] = accepted events of block m
+/* Workload histogram (Sec. 6, eq. wload): out[m] = accepted events of block m
  * (block order m = bj*NBX + bi) since the last fskmc_sim_init, set_lattice or
  * set_state.  n_blocks must equal the simulation's block count.  Synchronises
  * the context's stream. */
 int fskmc_sim_workload(fskmc_sim* sim, uint64_t* out, size_t n_blocks);
 
 /* Mass-transport map of a workload histogram W[0..M) onto P processors
- * (Sec. 5): bounds[0..P] (P+1 entries, caller-owned) with processor l owning
- * blocks [bounds[l], bounds[l+1]); bounds[l] is the first k with
+ * (Sec. 6, eq. wload and the map of its CDF onto equal masses):
+ * bounds[0..P] (P+1 entries, caller-owned) with processor l owning blocks
+ * [bounds[l], bounds[l+1]); bounds[l] is the first k with
  * P*(W[0] + ... + W[k-1]) >= l * total (a histogram without mass counts every
- * block once).  With cap > 0, when some range would hold more than cap
- * blocks the even split bounds[l] = floor(l*M/P) is returned instead.  Host
- * only.  FSKMC_EINVAL for M < 0, P < 1, cap < 0, NULL arrays or M > P*cap. */
+ * block once).  With cap > 0 every boundary is then clamped, in order l =
+ * 1..P-1, into [max(bounds[l-1], M - (P-l)*cap), min(bounds[l-1] + cap, M)],
+ * so no range holds more than cap blocks and the ranges still tile [0, M).
+ * Host only.  FSKMC_EINVAL for M < 0, P < 1, cap < 0, NULL arrays or
+ * M > P*cap. */
 int fskmc_workload_partition(const uint64_t* W, int M, int P, int cap, int32_t* bounds);
 
 /* The block ranges of the simulation's last rebalanced resident launch:
@@ -333,10 +343,15 @@ int fskmc_sim_last_partition(const fskmc_sim* sim, int32_t* out, size_t n, size_
 
 /* Failure handling: the longest time (seconds, in (0, 60], default 2) a block
  * of a persistent sweep waits for a neighbour before the sweep aborts; every
- * wave then leaves and the next synchronising call returns FSKMC_EDEVICE.
- * After that the simulation's lattice is unspecified until the next
- * fskmc_sim_init, fskmc_sim_set_lattice or fskmc_sim_set_state.  Tiny values
- * force the abort path (tests). */
+ * wave then leaves.  The context's abort flag is sticky: persistent launches
+ * enqueued after the aborted one leave at their first wait, and the next
+ * synchronising call (fskmc_sync, observe, get_lattice, get_state, workload,
+ * block_events, last_partition) returns FSKMC_EDEVICE and clears the flag.
+ * Every simulation a persistent launch advanced since the previous
+ * synchronising call is then invalid: its lattice is unspecified and
+ * advance, batch_advance, observe, get_lattice, get_state, workload and
+ * block_events return FSKMC_ESTATE until fskmc_sim_init or
+ * fskmc_sim_set_state.  Tiny values force the abort path (tests). */
 int fskmc_ctx_set_wait_limit(fskmc_ctx* ctx, double seconds);
 
 /* Measurement aid.  With stride > 0, every stride-th sweep launch on this

@@ -10,7 +10,7 @@ Plain, slow CPU reference implementations used to check the GPU library:
 * ``exact.py``: closed forms, finite transfer matrices and brute-force master
   equations that pin the oracle to the mathematics.
 * ``balance.py``: the workload histogram's mass-transport map onto equal
-  per-processor workloads (Sec. 5).
+  per-processor workloads (Sec. 6).
 
 Only ``tests/``, the smoke check and the CPU-baseline leg of the benchmark may
 import this package.  It shares no code with ``paper_1105_4673_amd``.

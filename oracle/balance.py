@@ -1,10 +1,10 @@
-"""Workload histogram and mass-transport rebalancing (Sec. 5) -- TEST
+"""Workload histogram and mass-transport rebalancing (Sec. 6) -- TEST
 INFRASTRUCTURE ONLY: the oracle of the library's workload partition.
 
 The workload W(m) of block m over a period is the number of jumps the block
-made in it (Sec. 5, eq. wload); normalised it is a histogram over the blocks.
+made in it (Sec. 6, eq. wload); normalised it is a histogram over the blocks.
 Rebalancing maps the mass of the cumulative distribution of W onto equal
-masses of the uniform distribution over P processors (Sec. 5): processor l
+masses of the uniform distribution over P processors (Sec. 6): processor l
 (l = 1..P) receives the blocks, taken in their given order, whose cumulative
 workload lies in the l-th of P equal slices of the total.  Written out on
 integers: with C(k) = W(0) + ... + W(k-1), boundary l is the smallest k with

@@ -1,4 +1,4 @@
-"""Nested (hierarchical) fractional-step decomposition (Sec. 6, eqs. sublatt2
+"""Nested (hierarchical) fractional-step decomposition (Sec. 5, eqs. sublatt2
 and opdecomp2) -- TEST INFRASTRUCTURE ONLY: the oracle of the library's
 nested schedule and colour map.
 

@@ -17,6 +17,7 @@
 
 #include "../../include/fskmc.h"
 #include "fskmc_internal.h"
+#include "fskmc_registry.h"
 
 using namespace fskmc;
 
@@ -91,8 +92,11 @@ struct fskmc_ctx {
     bool rebalance = false;      // resident launches: block ranges by the workload of the previous launch
     bool nested_kernel = true;   // nested sims: one workgroup per coarse cell and outer window
     unsigned long long wait_ticks = 200000000ull; // longest neighbour wait: 2 s of the 100 MHz wall clock
-    int32_t* d_abort = nullptr;  // raised by the persistent kernel on a timed-out wait
+    // Raised by a persistent kernel on a timed-out wait and sticky: cleared
+    // only by the synchronising call that reports it (check_abort).
+    int32_t* d_abort = nullptr;
     int32_t* h_abort = nullptr;  // pinned copy, refreshed after each persistent launch
+    SimRegistry<fskmc_sim> sims; // live sims, and those a pending persistent launch touched
     // batched advances: windows per persistent launch (0 = one packed launch
     // per window), HIP graph replay of the launch sequence, the work counter
     // of the persistent launches, and the cached graph with its layout key
@@ -105,6 +109,9 @@ struct fskmc_ctx {
 
 struct fskmc_sim {
     fskmc_ctx* ctx = nullptr;
+    // set when a persistent launch that advanced this sim aborted: the lattice
+    // is unspecified until fskmc_sim_init or fskmc_sim_set_state
+    bool invalid = false;
     int model = 0;
     fskmc_lattice lat{};
     double prm[5] = {0, 0, 0, 0, 0};
@@ -328,7 +335,7 @@ int build_schedule(fskmc_sim& S)
     return rc;
 }
 
-// Nested scheme (Sec. 6, eqs. sublatt2 and opdecomp2): the outer scheme of
+// Nested scheme (Sec. 5, eqs. sublatt2 and opdecomp2): the outer scheme of
 // step dt over the outer colours, each outer window (c, d) replaced by the
 // inner scheme of step dtau over the inner colours for time d, on flat colour
 // c * k_inner + inner colour.  step_end marks the end of every outer step.
@@ -564,7 +571,6 @@ int enqueue_nested_resident(fskmc_sim* S, uint64_t w0, uint64_t w1)
     const int cs = S->cx * S->bx;
     const int64_t words = (int64_t)S->NCX * S->NCY * (cs / 8);
     HIP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(S->d_edge), words, ~0ull, st));
-    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_abort), 1, 0u, st));
     NestedResArgs a{};
     a.lat = S->d_lat;
     a.table = S->d_table;
@@ -596,6 +602,7 @@ int enqueue_nested_resident(fskmc_sim* S, uint64_t w0, uint64_t w1)
     HIP_TRY(e);
     timing_end(c, tk);
     HIP_TRY(hipMemcpyAsync(c->h_abort, c->d_abort, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    c->sims.touched(S);
     for (uint64_t w = w0; w < w1; ++w) {
         const int co = S->win_colour[w] / S->k_inner;
         S->block_windows += (uint64_t)(S->cell_off[co + 1] - S->cell_off[co]) * (uint64_t)(S->cx * S->cy / S->k_inner);
@@ -627,14 +634,13 @@ int enqueue_window(fskmc_sim* S, uint64_t w)
 }
 
 // Windows [w0, w1) in one persistent kernel: epochs set to each block's first
-// window >= w0, the abort flag cleared, one cooperative launch, and the flag
-// copied back for the next synchronising call to check.
+// window >= w0, one cooperative launch, and the (sticky) abort flag copied
+// back for the next synchronising call to check.
 int enqueue_persistent(fskmc_sim* S, uint64_t w0, uint64_t w1)
 {
     fskmc_ctx* c = S->ctx;
     hipStream_t st = c->stream;
     HIP_TRY(launch_epoch_init(S->d_epoch, S->d_bcol, S->d_next, S->nb, (int)S->n_windows, (int)w0, st));
-    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_abort), 1, 0u, st));
     PersistArgs a;
     a.lat = S->d_lat;
     a.table = S->d_table;
@@ -661,6 +667,7 @@ int enqueue_persistent(fskmc_sim* S, uint64_t w0, uint64_t w1)
     HIP_TRY(launch_sweep_persistent(kernel_model(S->model), S->P, S->shape, c->wpg, a, S->max_per_colour, st, tk));
     timing_end(c, tk);
     HIP_TRY(hipMemcpyAsync(c->h_abort, c->d_abort, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    c->sims.touched(S);
     for (uint64_t w = w0; w < w1; ++w) {
         const int col = S->win_colour[w];
         S->block_windows += (uint64_t)(S->colour_off[col + 1] - S->colour_off[col]);
@@ -668,7 +675,7 @@ int enqueue_persistent(fskmc_sim* S, uint64_t w0, uint64_t w1)
     return FSKMC_OK;
 }
 
-// Mass-transport map of a workload histogram onto P processors (Sec. 5):
+// Mass-transport map of a workload histogram onto P processors (Sec. 6):
 // boundary l is the first k with P * (W[0] + ... + W[k-1]) >= l * total (a
 // histogram without mass counts every block once), clamped in order into
 // [max(b_{l-1}, M - (P-l) cap), min(b_{l-1} + cap, M)] when a capacity is
@@ -747,15 +754,13 @@ int rebalance_ranges(fskmc_sim* S, uint64_t w0)
 }
 
 // Windows [w0, w1) of a spin-flip simulation in one resident launch: edge
-// tags set to a value no window expects, the abort flag cleared, one
-// cooperative launch.  Returns 1 (nothing enqueued but the fill) when the
+// tags set to a value no window expects, one cooperative launch.  Returns 1 (nothing enqueued but the fill) when the
 // blocks do not fit the resident waves; the caller then streams.
 int enqueue_resident(fskmc_sim* S, uint64_t w0, uint64_t w1)
 {
     fskmc_ctx* c = S->ctx;
     hipStream_t st = c->stream;
     HIP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(S->d_edge), 4 * (int64_t)S->nb, ~0ull, st));
-    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_abort), 1, 0u, st));
     ResidentArgs a;
     a.lat = S->d_lat;
     a.table = S->d_table;
@@ -797,6 +802,7 @@ int enqueue_resident(fskmc_sim* S, uint64_t w0, uint64_t w1)
     HIP_TRY(e);
     timing_end(c, tk);
     HIP_TRY(hipMemcpyAsync(c->h_abort, c->d_abort, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    c->sims.touched(S);
     for (uint64_t w = w0; w < w1; ++w) {
         const int col = S->win_colour[w];
         S->block_windows += (uint64_t)(S->colour_off[col + 1] - S->colour_off[col]);
@@ -804,13 +810,29 @@ int enqueue_resident(fskmc_sim* S, uint64_t w0, uint64_t w1)
     return FSKMC_OK;
 }
 
-// After a stream synchronisation: did a persistent sweep abort?
+// After a stream synchronisation: did a persistent sweep abort since the
+// last check?  The flag is sticky on the device, so the copy taken after the
+// last persistent launch sees an abort of any earlier one.  On an abort every
+// sim a persistent launch advanced since the last check is marked invalid,
+// and the flag is cleared for the launches that follow.
 int check_abort(fskmc_ctx* c)
 {
-    if (c->h_abort && *c->h_abort) {
-        *c->h_abort = 0;
-        return fail(FSKMC_EDEVICE, "persistent sweep aborted: a neighbour wait timed out");
-    }
+    const bool aborted = c->h_abort && *c->h_abort;
+    for (fskmc_sim* S : c->sims.settle(aborted))
+        S->invalid = true;
+    if (!aborted)
+        return FSKMC_OK;
+    *c->h_abort = 0;
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_abort), 1, 0u, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return fail(FSKMC_EDEVICE, "persistent sweep aborted: a neighbour wait timed out");
+}
+
+int check_valid(const fskmc_sim* S)
+{
+    if (S->invalid)
+        return fail(FSKMC_ESTATE, "a persistent sweep of this simulation aborted: its lattice is unspecified until "
+                                  "fskmc_sim_init or fskmc_sim_set_state");
     return FSKMC_OK;
 }
 
@@ -890,6 +912,11 @@ int fskmc_ctx_create(int device, void* hip_stream, fskmc_ctx** out)
         return fail(FSKMC_ENOMEM, "context allocation failed");
     }
     *c->h_abort = 0;
+    if (launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_abort), 1, 0u, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        fskmc_ctx_destroy(c);
+        return fail(FSKMC_EDEVICE, "clearing the abort flag failed");
+    }
     *out = c;
     return FSKMC_OK;
 }
@@ -901,6 +928,11 @@ int fskmc_ctx_destroy(fskmc_ctx* c)
     (void)hipSetDevice(c->device);
     if (c->stream)
         (void)hipStreamSynchronize(c->stream);
+    // simulations still created on this context go with it
+    for (fskmc_sim* S : c->sims.release_all()) {
+        free_sim_device(S);
+        delete S;
+    }
     (void)hipFree(c->d_obs);
     (void)hipHostFree(c->h_obs);
     (void)hipFree(c->d_abort);
@@ -984,6 +1016,8 @@ int fskmc_sim_workload(fskmc_sim* S, uint64_t* out, size_t n_blocks)
         return fail(FSKMC_EINVAL, "NULL argument");
     if (n_blocks != (size_t)S->nb)
         return fail(FSKMC_EINVAL, "sim has %d blocks, got %zu", S->nb, n_blocks);
+    if (int rc = check_valid(S))
+        return rc;
     std::vector<BlockCount> rec(n_blocks);
     HIP_TRY(hipMemcpyAsync(rec.data(), S->d_cnt, n_blocks * sizeof(BlockCount), hipMemcpyDeviceToHost,
                            S->ctx->stream));
@@ -1296,6 +1330,7 @@ int sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const vo
         delete S;
         return e != hipSuccess ? fail(FSKMC_EDEVICE, "sim upload failed: %s", hipGetErrorString(e)) : rc;
     }
+    ctx->sims.add(S);
     *out = S;
     return FSKMC_OK;
 }
@@ -1322,6 +1357,7 @@ int fskmc_sim_destroy(fskmc_sim* S)
         return FSKMC_OK;
     (void)hipSetDevice(S->ctx->device);
     (void)hipStreamSynchronize(S->ctx->stream);
+    S->ctx->sims.remove(S);
     free_sim_device(S);
     delete S;
     return FSKMC_OK;
@@ -1357,6 +1393,7 @@ int fskmc_sim_init(fskmc_sim* S, int kind, double p)
         return fail(FSKMC_EINVAL, "Bernoulli p must be in [0,1]");
     HIP_TRY(launch_init(S->d_lat, n_sites(S->lat), kind, p, S->key.seed, S->key.replica, S->ctx->stream));
     S->window = 0;
+    S->invalid = false;
     return reset_counters(S);
 }
 
@@ -1381,6 +1418,8 @@ int fskmc_sim_get_lattice(fskmc_sim* S, uint8_t* host, size_t n)
         return fail(FSKMC_EINVAL, "NULL argument");
     if (n != (size_t)n_sites(S->lat))
         return fail(FSKMC_EINVAL, "lattice has %lld sites, got %zu bytes", (long long)n_sites(S->lat), n);
+    if (int rc = check_valid(S))
+        return rc;
     HIP_TRY(hipMemcpyAsync(host, S->d_lat, n, hipMemcpyDeviceToHost, S->ctx->stream));
     HIP_TRY(hipStreamSynchronize(S->ctx->stream));
     return check_abort(S->ctx);
@@ -1390,6 +1429,8 @@ int fskmc_sim_advance(fskmc_sim* S, uint64_t n_windows)
 {
     if (!S)
         return fail(FSKMC_EINVAL, "sim is NULL");
+    if (int rc = check_valid(S))
+        return rc;
     if (n_windows > S->n_windows - S->window)
         return fail(FSKMC_ESTATE, "only %llu windows left before T", (unsigned long long)(S->n_windows - S->window));
     if (S->nested && S->nest_kernel_ok && S->ctx->nested_kernel) {
@@ -1462,6 +1503,8 @@ int fskmc_sim_observe(fskmc_sim* S, fskmc_obs* out)
 {
     if (!S || !out)
         return fail(FSKMC_EINVAL, "NULL argument");
+    if (int rc = check_valid(S))
+        return rc;
     fskmc_ctx* c = S->ctx;
     HIP_TRY(launch_fill_u64((uint64_t*)c->d_obs, 9, 0ull, c->stream));
     HIP_TRY(launch_observe(S->d_lat, S->lat.Lx, S->lat.Ly, S->lat.dim, S->d_cnt, S->nb, c->d_obs,
@@ -1495,13 +1538,15 @@ int fskmc_sim_block_events(fskmc_sim* S, uint32_t* out, size_t n_blocks)
         return fail(FSKMC_EINVAL, "NULL argument");
     if (n_blocks != (size_t)S->nb)
         return fail(FSKMC_EINVAL, "sim has %d blocks, got %zu", S->nb, n_blocks);
+    if (int rc = check_valid(S))
+        return rc;
     std::vector<BlockCount> rec(n_blocks);
     HIP_TRY(hipMemcpyAsync(rec.data(), S->d_cnt, n_blocks * sizeof(BlockCount), hipMemcpyDeviceToHost,
                            S->ctx->stream));
     HIP_TRY(hipStreamSynchronize(S->ctx->stream));
     for (size_t i = 0; i < n_blocks; ++i)
         out[i] = rec[i].W;
-    return FSKMC_OK;
+    return check_abort(S->ctx);
 }
 
 int fskmc_sim_rate_table(const fskmc_sim* S, double* out, size_t n)
@@ -1536,6 +1581,7 @@ int fskmc_sim_set_state(fskmc_sim* S, uint64_t window, const uint8_t* host, size
     if (rc)
         return rc;
     S->window = window;
+    S->invalid = false;
     return reset_counters(S);
 }
 
@@ -1562,6 +1608,8 @@ int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t 
     for (int i = 0; i < n; ++i) {
         if (!sims[i] || sims[i]->ctx != ctx)
             return fail(FSKMC_EINVAL, "sim %d is NULL or belongs to another context", i);
+        if (int rc = check_valid(sims[i]))
+            return rc;
         for (int j = 0; j < i; ++j)
             if (sims[j] == sims[i])
                 return fail(FSKMC_EINVAL, "sim %d appears twice", i);
@@ -1686,9 +1734,7 @@ int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t 
                 }
             return e;
         }
-        e = launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->d_abort), 1, 0u, st);
-        if (e == hipSuccess)
-            e = launch_epoch_init_batched(ctx->d_jobs, (int)n_jobs, st);
+        e = launch_epoch_init_batched(ctx->d_jobs, (int)n_jobs, st);
         for (uint32_t s0 = 0; s0 < windows && e == hipSuccess; s0 += K) {
             const uint32_t s1 = std::min<uint32_t>(windows, s0 + K);
             for (auto& g : groups) {
@@ -1718,8 +1764,10 @@ int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t 
         return e;
     };
     if (ctx->graphs && ctx->timing_stride == 0) {
+        // everything the captured launches bake in, the wait limit included
         std::vector<uint64_t> key = {windows, K, (uint64_t)ctx->wpg, (uint64_t)(uintptr_t)ctx->d_jobs,
-                                     (uint64_t)(uintptr_t)ctx->d_items, (uint64_t)(uintptr_t)st, n_jobs};
+                                     (uint64_t)(uintptr_t)ctx->d_items, (uint64_t)(uintptr_t)st, n_jobs,
+                                     (uint64_t)ctx->wait_ticks};
         for (auto& g : groups)
             key.insert(key.end(), {(uint64_t)g.model, (uint64_t)g.P, (uint64_t)g.shape, g.job_off, g.item_off,
                                    g.items, g.idx.size()});
@@ -1754,6 +1802,8 @@ int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t 
         HIP_TRY(hipMemcpyAsync(ctx->h_abort, ctx->d_abort, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     for (int i = 0; i < n; ++i) {
         fskmc_sim* S = sims[i];
+        if (K > 0 && S->window < S->n_windows)
+            ctx->sims.touched(S);
         const uint64_t end = std::min<uint64_t>(S->n_windows, S->window + windows);
         for (uint64_t w = S->window; w < end; ++w) {
             const int c = S->win_colour[w];

@@ -117,7 +117,7 @@ struct ResidentArgs {
     unsigned long long wait_ticks;
 };
 
-// Nested sweep (Sec. 6, eqs. sublatt2 and opdecomp2): one workgroup per coarse
+// Nested sweep (Sec. 5, eqs. sublatt2 and opdecomp2): one workgroup per coarse
 // cell of the active outer colour; the cell's fine blocks (one wave each per
 // inner window) share one LDS tile and run the inner windows [w0, w1) of one
 // outer window separated by workgroup barriers.

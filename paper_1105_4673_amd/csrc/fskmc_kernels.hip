@@ -1456,7 +1456,7 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Nested sweep (Sec. 6, eqs. sublatt2 and opdecomp2).  A coarse cell of C x C
+// Nested sweep (Sec. 5, eqs. sublatt2 and opdecomp2).  A coarse cell of C x C
 // fine blocks is one workgroup; its tile (cell plus the one-site ring of the
 // neighbouring cells, frozen for the outer window) is staged once into LDS.
 // In every inner window the blocks of the active inner colour run their SSA
@@ -1597,7 +1597,7 @@ __global__ __launch_bounds__(64 * (CC * CC / KI)) void k_sweep_nested(NestedArgs
     }
 }
 
-// Resident nested sweep (spin flip; Sec. 6 with the local synchronisation of
+// Resident nested sweep (spin flip; Sec. 5 with the local synchronisation of
 // Sec. 2.2 at the coarse level).  Every coarse cell is one workgroup for the
 // whole launch and keeps its tile in LDS; the lattice is read once at the
 // start and written once at the end.  The cell's four one-site boundary
@@ -1763,7 +1763,7 @@ __global__ __launch_bounds__(64 * (CC * CC / KI)) void k_sweep_nested_resident(N
 
 // ---------------------------------------------------------------------------
 // Block ranges of the next resident launch from the workload of the previous
-// one (Sec. 5: the cumulative distribution of the workload histogram mapped
+// one (Sec. 6: the cumulative distribution of the workload histogram mapped
 // onto equal masses over the processors), in one workgroup between launches.
 // cost(m) = jumps of block m since the previous launch + base x (windows of
 // its colour in that launch), or 1 for every block on the first launch; the

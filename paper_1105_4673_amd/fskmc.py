@@ -4,8 +4,10 @@ The functions below carry the C names and only marshal arguments: every step
 of the fractional-step path runs in the HIP library.  Importing this module
 raises if libfskmc.so has not been built; there is no fallback.
 """
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -144,15 +146,40 @@ def _u8p(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
 
 
+# Contexts created through this module and the Sim objects made on each:
+# fskmc_ctx_destroy releases a context's remaining simulations in the library,
+# so their Python objects are closed here at the same moment (a later close()
+# is then a no-op instead of a use of freed memory), and contexts still open
+# when the interpreter exits are destroyed before the HIP runtime goes away.
+_contexts = {}
+
+
+def _ctx_key(ctx):
+    return ctx.value if isinstance(ctx, ctypes.c_void_p) else int(ctx)
+
+
 # --- thin wrappers with the C names -----------------------------------------
 def fskmc_ctx_create(device=0, hip_stream=None):
     out = ctypes.c_void_p()
     _check(lib.fskmc_ctx_create(device, hip_stream, ctypes.byref(out)))
+    _contexts[out.value] = weakref.WeakSet()
     return out
 
 
 def fskmc_ctx_destroy(ctx):
+    key = _ctx_key(ctx)
+    for sim in list(_contexts.pop(key, ())):
+        sim.handle = None  # released by the library together with the context
     _check(lib.fskmc_ctx_destroy(ctx))
+
+
+@atexit.register
+def _destroy_open_contexts():
+    for key in list(_contexts):
+        try:
+            fskmc_ctx_destroy(ctypes.c_void_p(key))
+        except Exception:
+            pass
 
 
 def fskmc_ctx_set_waves_per_group(ctx, waves):
@@ -384,11 +411,16 @@ class Sim:
                                            split, seed, replica, colour_map)
         self.N = Lx * Ly
         self.nb = (Lx // bx) * (Ly // by)
+        live = _contexts.get(_ctx_key(ctx))
+        if live is not None:
+            live.add(self)
 
     def close(self):
+        """Destroy the simulation; a no-op once closed or once its context
+        has been destroyed (which released it)."""
         if self.handle is not None:
-            fskmc_sim_destroy(self.handle)
-            self.handle = None
+            handle, self.handle = self.handle, None
+            fskmc_sim_destroy(handle)
 
     def __del__(self):
         try:

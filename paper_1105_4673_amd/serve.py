@@ -94,6 +94,7 @@ class Server:
         self.rejected = []
         self.used = 0
         self.steps = 0
+        self.max_resident = 0
 
     def submit(self, req):
         req.footprint = self.b.footprint(req.spec)
@@ -155,6 +156,7 @@ class Server:
         now = self.clock()
         self._admit(now)
         if self.resident:
+            self.max_resident = max(self.max_resident, len(self.resident))
             self.b.advance([r.handle for r in self.resident], self.k)
             self.steps += 1
             self._retire()

@@ -1,5 +1,5 @@
 """The library's workload partition (host code behind the C ABI, no GPU
-needed) equals the oracle's mass-transport map (Sec. 5) element by element,
+needed) equals the oracle's mass-transport map (Sec. 6) element by element,
 on random histograms with idle stretches, spikes and capacities, on the
 extreme sizes the resident sweep uses, and rejects invalid inputs."""
 import numpy as np

@@ -1,7 +1,12 @@
-"""Batched advances (needs a GPU): the persistent batched sweep (K windows of
-every sim per launch, work items from a device counter) and HIP-graph replay
-of the batch's launch sequence give every sim the bits it gets alone."""
+"""Batched advances (needs a GPU): one packed launch per window (the
+full-launch and the 16-sites-per-lane small-launch kernels), the persistent
+batched sweep (K windows of every sim per launch, work items from a device
+counter) and HIP-graph replay of the batch's launch sequence give every sim
+the oracle's bits (final lattice and event total of the blockwise scheme,
+Sec. 2.2 eq. exact) and the bits it gets alone."""
 import hashlib
+import os
+import sys
 
 import numpy as np
 import pytest
@@ -54,6 +59,16 @@ def _digest(s):
     return hashlib.sha256(s.lattice().tobytes()).hexdigest(), s.observe()["events"]
 
 
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from _oracle_jobs import oracle_result  # noqa: E402
+
+
+def _oracle(orc, specs):
+    """The oracle's (sha256, events) of each whole run; _make starts every
+    sim from the Bernoulli(1/2) state."""
+    return [oracle_result(orc, dict(sp, init="bernoulli")) for sp in specs]
+
+
 def _alone(F, ctx, specs):
     out = []
     for s in _make(F, ctx, specs):
@@ -63,10 +78,14 @@ def _alone(F, ctx, specs):
     return out
 
 
-@pytest.mark.parametrize("K", [1, 3, 50])
+@pytest.mark.parametrize("K", [0, 1, 3, 50])
 @pytest.mark.parametrize("graphs", [1, 0], ids=["graph", "eager"])
-def test_batch_persistent_equals_alone(F, ctx, K, graphs):
+def test_batch_persistent_equals_alone(F, orc, ctx, K, graphs):
+    """K = 0: one packed launch per window (k_sweep_batched; the reaction job
+    of 32x32 blocks takes the small-launch kernel for 16 sites per lane);
+    K > 0: k_sweep_batched_persistent, K windows per launch."""
     want = _alone(F, ctx, SPECS)
+    assert want == _oracle(orc, SPECS)
     F.fskmc_ctx_set_batch_persistent(ctx, K)
     F.fskmc_ctx_set_graphs(ctx, graphs)
     sims = _make(F, ctx, SPECS)
@@ -80,15 +99,18 @@ def test_batch_persistent_equals_alone(F, ctx, K, graphs):
     assert got == want
 
 
-def test_batch_full_and_small_launch_kernels(F, ctx):
+def test_batch_full_and_small_launch_kernels(F, orc, ctx):
     """16 sites per lane in both launch kernels at once: the spin-flip group
     holds 2112 blocks per window (the full-launch kernel), the reaction group
-    16 (the small-launch kernel); every sim gets the bits it gets alone."""
+    16 (the small-launch kernel); every sim gets the oracle's bits (the
+    2112x2048 run's stored value, the reaction job's computed here) and the
+    bits it gets alone."""
     specs = [dict(kind=FLIP, Lx=2112, Ly=2048, params=(1.0, 1.0, 0.8, -0.2, 1.0), b=32, n_colours=2, dt=0.2, T=1.0,
                   split=0, seed=0, replica=21),
              dict(kind=ZGB, Lx=256, Ly=256, params=(0.5, 1000.0, 10.0), b=32, n_colours=4, dt=0.05, T=0.5, split=1,
                   seed=0, replica=22)]
     want = _alone(F, ctx, specs)
+    assert want == _oracle(orc, specs)
     F.fskmc_ctx_set_batch_persistent(ctx, 0)
     sims = _make(F, ctx, specs)
     while any(s.windows()[1] < s.windows()[0] for s in sims):
@@ -101,7 +123,7 @@ def test_batch_full_and_small_launch_kernels(F, ctx):
 
 
 @pytest.mark.parametrize("K", [0, 4])
-def test_graph_replays_match_eager(F, ctx, K):
+def test_graph_replays_match_eager(F, orc, ctx, K):
     """Two copies of one batch, one replaying a captured graph and one
     launching eagerly, compared after every call (each call uploads a new job
     table and synchronises between the replays)."""
@@ -120,11 +142,12 @@ def test_graph_replays_match_eager(F, ctx, K):
             np.testing.assert_array_equal(x.lattice(), y.lattice())
         calls += 1
     assert calls >= 3
+    assert [_digest(x) for x in a] == _oracle(orc, SPECS[:4])
     for s in a + b:
         s.close()
 
 
-def test_batch_persistent_wait_timeout_reports_edevice(F, ctx):
+def test_batch_persistent_wait_timeout_reports_edevice(F, orc, ctx):
     """A wait limit far below one window forces the bounded neighbour wait to
     give up: the launch aborts, every wave leaves, the next synchronising call
     reports FSKMC_EDEVICE, and the context works again afterwards."""
@@ -145,7 +168,7 @@ def test_batch_persistent_wait_timeout_reports_edevice(F, ctx):
     while sims[0].windows()[1] < sims[0].windows()[0]:
         F.fskmc_batch_advance(ctx, [sims[0].handle], 9)
     F.fskmc_sync(ctx)
-    assert [_digest(sims[0])] == want
+    assert [_digest(sims[0])] == want == _oracle(orc, SPECS[:1])
     sims[0].close()
 
 

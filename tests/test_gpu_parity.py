@@ -559,7 +559,7 @@ def test_persistent_wait_timeout_reports_edevice(F, ctx, resident):
 
 @pytest.mark.parametrize("L,chunk", [(512, 25), (2048, 10)], ids=["512-pairs", "2048-capacity-bound"])
 def test_rebalanced_resident(F, ctx, L, chunk):
-    """Workload rebalancing (Sec. 5) on a half-filled lattice (the empty half
+    """Workload rebalancing (Sec. 6) on a half-filled lattice (the empty half
     adsorbs, the full half is nearly idle): every resident launch takes its
     block ranges from the oracle's mass-transport map of the block costs of
     the previous launch (jumps plus 3 per window of the block's colour; an

@@ -1,11 +1,16 @@
-"""Served jobs give the same bits as the same jobs run alone (needs a GPU).
+"""Served jobs give the oracle's bits, and the same bits as the same jobs
+run alone (needs a GPU).
 
 A mixed stream of spin-flip and reaction-model jobs of different sizes and
 schedules goes through the continuous-batching server with a budget that
-forces queueing; afterwards every job is rerun alone with a plain run and its
-final lattice and event count must be identical.
+forces queueing, so jobs are admitted while others run and share their
+launches; every job's final lattice and event count must equal the oracle's
+blockwise fractional-step run of the same job (Sec. 2.2 eq. exact) and a
+plain run of the job alone.
 """
 import hashlib
+import os
+import sys
 
 import numpy as np
 import pytest
@@ -32,7 +37,11 @@ def _specs():
     return out
 
 
-def test_served_equals_alone():
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from _oracle_jobs import oracle_result  # noqa: E402
+
+
+def test_served_equals_alone(orc):
     from paper_1105_4673_amd import fskmc as F
     from paper_1105_4673_amd.serve import GpuBackend, Request, Server, summarize
     ctx = F.fskmc_ctx_create(0)
@@ -46,8 +55,12 @@ def test_served_equals_alone():
         assert len(done) == len(specs) and all(r.status == "done" for r in done)
         s = summarize(done, wall=max(r.finished for r in done))
         assert s["events"] > 0 and s["p99_time_to_result_s"] >= s["p50_time_to_result_s"]
+        # continuous batching: some job was admitted while another was resident
+        # (its run overlapped the other's on the device)
+        assert any(q.admitted < r.admitted < q.finished for r in done for q in done if q is not r)
         for r in done:
             sp = r.spec
+            assert (r.result["digest"], r.result["events"]) == oracle_result(orc, sp), r.rid
             sim = F.Sim(ctx, sp["kind"], sp["Lx"], sp["Ly"], sp["params"], b=sp["b"], n_colours=sp["n_colours"],
                         dt=sp["dt"], T=sp["T"], split=sp["split"], seed=sp["seed"], replica=sp["replica"])
             sim.init(1 if sp["init"] == "bernoulli" else 0, 0.5)

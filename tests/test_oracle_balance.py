@@ -1,4 +1,4 @@
-"""Pins for the oracle's workload rebalancing (Sec. 5), independent of its code:
+"""Pins for the oracle's workload rebalancing (Sec. 6), independent of its code:
 
 * a uniform histogram over M = k P blocks splits into P equal ranges;
 * each processor's workload is below total / P + max W (the CDF map puts at

@@ -1,4 +1,4 @@
-"""Pins for the oracle's nested (hierarchical) decomposition (Sec. 6, eqs.
+"""Pins for the oracle's nested (hierarchical) decomposition (Sec. 5, eqs.
 sublatt2 and opdecomp2), independent of its code:
 
 * window lists and colour maps of small cases, written out by hand from the
