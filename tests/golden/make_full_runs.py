@@ -63,6 +63,9 @@ CASES = {
                                                         0.05, 10.0, "empty", 0, 1, 280),
     "reaction1024_b32_y0.5_D10_strang_dt0.05_T10_r1": ("zgb", 1024, 1024, _zgb(0.5, 10.0), 32, 4, orc.STRANG, 0.05,
                                                        10.0, "empty", 0, 1, None),
+    # the 1024^2 job of the batched-kernel tests (whole run)
+    "ising1024_b16_J1_lie_dt0.1_T1_r7": ("flip", 1024, 1024, _flip(1.0), 16, 2, orc.LIE, 0.1, 1.0, "bernoulli", 0, 7,
+                                         None),
     # the full- and small-launch batched kernels' spin-flip job (whole run)
     "ising2112x2048_b32_J0.8_h-0.2_lie_dt0.2_T1_r21": ("flip", 2112, 2048, _flip(0.8, -0.2), 32, 2, orc.LIE, 0.2,
                                                        1.0, "bernoulli", 0, 21, None),

@@ -506,11 +506,12 @@ def test_full_run_matches_oracle_golden(F, ctx, name, persist):
     import hashlib
     g = _FULL[name]
     p = g["params"]
-    prm = ((p["k_a"], p["k_d"], p["J"], p["h"], p["beta"]) if g["kind"] == "flip" else (p["y"], p["k_r"], p["D"]))
+    prm = ((p["k_a"], p["k_d"], p["J"], p["h"], p["beta"]) if g["kind"] == "flip" else
+           (p["D"], p["J"], p["beta"]) if g["kind"] == "kawasaki" else (p["y"], p["k_r"], p["D"]))
     F.fskmc_ctx_set_persistent(ctx, g["windows"] if persist else 0)
     F.fskmc_ctx_set_resident(ctx, persist != 2)
     try:
-        s = F.Sim(ctx, g["kind"], g["L"], g["L"], prm, b=g["b"], n_colours=g["n_colours"], dt=g["dt"], T=g["T"],
+        s = F.Sim(ctx, g["kind"], g.get("Lx", g["L"]), g.get("Ly", g["L"]), prm, b=g["b"], n_colours=g["n_colours"], dt=g["dt"], T=g["T"],
                   split=g["split"], seed=g["seed"], replica=g["replica"])
         s.init(1 if g["init"] == "bernoulli" else 0, 0.5)
         s.advance(g["windows"])
