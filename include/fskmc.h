@@ -362,6 +362,36 @@ int fskmc_ctx_set_wait_limit(fskmc_ctx* ctx, double seconds);
 int fskmc_ctx_set_kernel_timing(fskmc_ctx* ctx, int stride);
 int fskmc_ctx_read_kernel_timing(fskmc_ctx* ctx, double* total_ms, uint64_t* n_launches);
 
+/* Allocation-free advance, for callers that cannot allocate device memory at
+ * call time: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  It runs windows [w0, w0 + n_windows) of the scheme that
+ * fskmc_sim_create would build from the same arguments, one launch per window
+ * with the kernels of fskmc_sim_advance, on a lattice the caller owns, and
+ * gives the same bits.
+ *  - device, hip_stream: the GPU and the stream the work is enqueued on (NULL
+ *    = that device's null stream).  Asynchronous: nothing is waited for, and
+ *    the only HIP calls are kernel launches (no allocation, copy or memset).
+ *  - lattice, model, params, schedule, key: as for fskmc_sim_create; decomp
+ *    must use a built-in map (colour_map NULL, 2 or 4 colours).
+ *  - d_lattice: device pointer, Lx*Ly bytes (site y*Lx + x), the state at
+ *    window w0 on entry and after the last window on completion.
+ *  - d_block_events: optional device pointer, n_blocks uint32 (block m =
+ *    bj*NBX + bi): accepted events of each block's last window in this call,
+ *    0 for blocks that ran none.  d_events: optional device pointer to one
+ *    uint64, the call's accepted events.  Both written, not accumulated.
+ * Working memory is a static device array of 1.36 MB per GPU (the rate
+ * table, block lists and per-block counters), held until the process ends;
+ * at most 65536 blocks per lattice (FSKMC_EINVAL beyond).  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialised by the caller.
+ * FSKMC_EINVAL / FSKMC_EDECOMP as fskmc_sim_create, FSKMC_ESTATE if the
+ * windows run past T, FSKMC_EDEVICE if a launch fails; arguments are checked
+ * before any HIP call. */
+int fskmc_advance_noalloc(int device, void* hip_stream, const fskmc_lattice* lattice, int model, const void* params,
+                          const fskmc_decomp* decomp, const fskmc_schedule* schedule, fskmc_key key,
+                          uint8_t* d_lattice, uint64_t w0, uint64_t n_windows, uint32_t* d_block_events,
+                          unsigned long long* d_events);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfskmc.so")
-SOURCES = [os.path.join(HERE, "csrc", "fskmc_kernels.hip"), os.path.join(HERE, "csrc", "fskmc_host.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", "fskmc_kernels.hip"), os.path.join(HERE, "csrc", "fskmc_noalloc.hip"),
+           os.path.join(HERE, "csrc", "fskmc_host.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -ffp-contract=off: the decision path must round like the CPU statement of the

@@ -274,6 +274,45 @@ int check_decomposition(const fskmc_sim& S)
     return FSKMC_OK;
 }
 
+// Window i of a step of one splitting scheme over K colours with step dt; w is
+// its index in the whole window list (the random schedule's Philox counter).
+void scheme_window(int split, int K, double dt, fskmc_key key, int i, uint32_t w, int* c, double* d)
+{
+    if (split == FSKMC_LIE) {
+        *c = i;
+        *d = dt;
+    } else if (split == FSKMC_STRANG) {
+        *c = i < K ? i : 2 * (K - 1) - i;
+        *d = *c == K - 1 ? dt : 0.5 * dt;
+    } else {
+        uint32_t ctr[4] = {w, 0u, 0u, 3u};
+        philox_host(ctr, key.seed, key.replica);
+        const uint64_t b = ((uint64_t)ctr[2] << 32) | ctr[3];
+        const double V = (double)(b >> 11) * 0x1p-53;
+        *c = (int)(V * (double)K);
+        *d = dt;
+    }
+}
+
+// Number of steps T / dt of a schedule (an integer within 1e-9, relative),
+// and the windows per step of the splitting.
+int scheme_steps(int split, int K, double dt, double T, int64_t* steps, int* per)
+{
+    if (!(dt > 0.0) || !(T >= 0.0) || !std::isfinite(dt) || !std::isfinite(T))
+        return fail(FSKMC_EINVAL, "need dt > 0 and T >= 0");
+    const double nd = std::floor(T / dt + 0.5);
+    if (std::fabs(nd * dt - T) > 1e-9 * std::max(1.0, T))
+        return fail(FSKMC_EINVAL, "T / dt = %.17g is not an integer", T / dt);
+    if (split != FSKMC_LIE && split != FSKMC_STRANG && split != FSKMC_RANDOM)
+        return fail(FSKMC_EINVAL, "unknown splitting %d", split);
+    const int64_t max_windows = INT32_MAX - 1;
+    *per = split == FSKMC_STRANG ? 2 * K - 1 : K;
+    if (nd > (double)max_windows || (int64_t)nd * *per > max_windows)
+        return fail(FSKMC_EINVAL, "more than %lld windows", (long long)max_windows);
+    *steps = (int64_t)nd;
+    return FSKMC_OK;
+}
+
 // Windows of one splitting scheme over K colours with step dt up to time T,
 // appended to (col, dur, end); w0 is the index of the first of them in the
 // whole list (the random schedule's Philox counter).
@@ -294,7 +333,6 @@ int scheme_windows(int split, int K, double dt, double T, fskmc_key key, uint64_
     if (nd > (double)max_windows || (int64_t)w0 + (int64_t)nd * per > max_windows)
         return fail(FSKMC_EINVAL, "more than %lld windows", (long long)max_windows);
     const int64_t steps = (int64_t)nd;
-    const double half = 0.5 * dt;
     col.reserve(col.size() + (size_t)(steps * per));
     dur.reserve(dur.size() + (size_t)(steps * per));
     uint32_t w = (uint32_t)w0;
@@ -302,20 +340,7 @@ int scheme_windows(int split, int K, double dt, double T, fskmc_key key, uint64_
         for (int i = 0; i < per; ++i, ++w) {
             int c;
             double d;
-            if (split == FSKMC_LIE) {
-                c = i;
-                d = dt;
-            } else if (split == FSKMC_STRANG) {
-                c = i < K ? i : 2 * (K - 1) - i;
-                d = c == K - 1 ? dt : half;
-            } else {
-                uint32_t ctr[4] = {w, 0u, 0u, 3u};
-                philox_host(ctr, key.seed, key.replica);
-                const uint64_t b = ((uint64_t)ctr[2] << 32) | ctr[3];
-                const double V = (double)(b >> 11) * 0x1p-53;
-                c = (int)(V * (double)K);
-                d = dt;
-            }
+            scheme_window(split, K, dt, key, i, w, &c, &d);
             col.push_back((int8_t)c);
             dur.push_back(d);
             end.push_back(i == per - 1 ? 1 : 0);
@@ -375,21 +400,28 @@ int build_nested_schedule(fskmc_sim& S)
     return FSKMC_OK;
 }
 
-void build_table(fskmc_sim& S)
+// Entries of a model's rate table: 2 (z + 1) for spin flip, 243 x 14 for the
+// pair-event models.
+inline int table_size(int model, int dim)
 {
-    if (S.model == FSKMC_MODEL_FLIP) {
-        const int z = S.lat.dim == 1 ? 2 : 4;
-        const double ka = S.prm[0], kd = S.prm[1], J = S.prm[2], h = S.prm[3], beta = S.prm[4];
-        S.table.assign(2 * (z + 1), 0.0);
+    return model == FSKMC_MODEL_FLIP ? 2 * (2 * dim + 1) : 243 * 14;
+}
+
+// The FP64 rate table of a model into tab (table_size entries).
+void fill_table(int model, int dim, const double prm[5], double* tab)
+{
+    std::fill(tab, tab + table_size(model, dim), 0.0);
+    if (model == FSKMC_MODEL_FLIP) {
+        const int z = dim == 1 ? 2 : 4;
+        const double ka = prm[0], kd = prm[1], J = prm[2], h = prm[3], beta = prm[4];
         for (int n = 0; n <= z; ++n) {
-            S.table[n] = ka;
-            S.table[(z + 1) + n] = kd * std::exp(-(beta * (J * (double)n + h)));
+            tab[n] = ka;
+            tab[(z + 1) + n] = kd * std::exp(-(beta * (J * (double)n + h)));
         }
-    } else if (S.model == FSKMC_MODEL_KAWASAKI) {
+    } else if (model == FSKMC_MODEL_KAWASAKI) {
         // Exchange uses the hop channels 9..12 of the pair-event table; the
         // barrier counts the occupied neighbours of the moving particle.
-        const double D = S.prm[0], J = S.prm[1], beta = S.prm[2];
-        S.table.assign(243 * 14, 0.0);
+        const double D = prm[0], J = prm[1], beta = prm[2];
         for (int pat = 0; pat < 243; ++pat) {
             int r = pat;
             const int s = r % 3;
@@ -400,7 +432,7 @@ void build_table(fskmc_sim& S)
                 r /= 3;
                 n += nb[d] == 1;
             }
-            double* ch = &S.table[(size_t)pat * 14];
+            double* ch = &tab[(size_t)pat * 14];
             for (int d = 0; d < 4; ++d)
                 if (s == 1 && nb[d] == 0)
                     ch[9 + d] = (D / 4.0) * std::exp(-(beta * (J * (double)n)));
@@ -410,8 +442,7 @@ void build_table(fskmc_sim& S)
             ch[13] = tot;
         }
     } else {
-        const double y = S.prm[0], kr = S.prm[1], D = S.prm[2];
-        S.table.assign(243 * 14, 0.0);
+        const double y = prm[0], kr = prm[1], D = prm[2];
         for (int pat = 0; pat < 243; ++pat) {
             int r = pat;
             const int s = r % 3;
@@ -421,7 +452,7 @@ void build_table(fskmc_sim& S)
                 nb[d] = r % 3;
                 r /= 3;
             }
-            double* ch = &S.table[(size_t)pat * 14];
+            double* ch = &tab[(size_t)pat * 14];
             if (s == 0)
                 ch[0] = y;
             for (int d = 0; d < 4; ++d) {
@@ -438,6 +469,22 @@ void build_table(fskmc_sim& S)
             ch[13] = tot;
         }
     }
+}
+
+void build_table(fskmc_sim& S)
+{
+    S.table.assign((size_t)table_size(S.model, S.lat.dim), 0.0);
+    fill_table(S.model, S.lat.dim, S.prm, S.table.data());
+}
+
+// Every rate finite and small enough that a block's total stays finite (an
+// infinite total would give zero waiting times and a window that never ends).
+int check_table(const double* tab, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(tab[i]) || tab[i] < 0.0 || !std::isfinite(tab[i] * 4096.0))
+            return fail(FSKMC_EINVAL, "rate %g is not finite or too large", tab[i]);
+    return FSKMC_OK;
 }
 
 template <class T>
@@ -1123,6 +1170,39 @@ int check_coarse(const fskmc_sim& S)
     return rc ? fail(rc, "coarse cells of one outer colour interact: %s", fskmc_last_error()) : FSKMC_OK;
 }
 
+// The model's parameters into prm[0..4] (spin flip: k_a, k_d, J, h, beta;
+// reaction model: y, k_r, D; spin exchange: D, J, beta), checked.
+int parse_params(int model, const void* params, double prm[5])
+{
+    for (int i = 0; i < 5; ++i)
+        prm[i] = 0.0;
+    if (model == FSKMC_MODEL_FLIP) {
+        const fskmc_flip_params* p = (const fskmc_flip_params*)params;
+        double v[5] = {p->k_a, p->k_d, p->J, p->h, p->beta};
+        for (int i = 0; i < 5; ++i)
+            prm[i] = v[i];
+        if (!(p->k_a >= 0) || !(p->k_d >= 0) || !std::isfinite(p->J) || !std::isfinite(p->h) ||
+            !std::isfinite(p->beta) || !std::isfinite(p->k_a) || !std::isfinite(p->k_d))
+            return fail(FSKMC_EINVAL, "spin-flip rates must be finite and k_a, k_d >= 0");
+    } else if (model == FSKMC_MODEL_KAWASAKI) {
+        const fskmc_kawasaki_params* p = (const fskmc_kawasaki_params*)params;
+        prm[0] = p->D;
+        prm[1] = p->J;
+        prm[2] = p->beta;
+        if (!(p->D >= 0) || !std::isfinite(p->D) || !std::isfinite(p->J) || !std::isfinite(p->beta))
+            return fail(FSKMC_EINVAL, "spin exchange needs D >= 0 and finite D, J, beta");
+    } else {
+        const fskmc_zgb_params* p = (const fskmc_zgb_params*)params;
+        prm[0] = p->y;
+        prm[1] = p->k_r;
+        prm[2] = p->D;
+        if (!(p->y >= 0 && p->y <= 1) || !(p->k_r >= 0) || !(p->D >= 0) || !std::isfinite(p->k_r) ||
+            !std::isfinite(p->D))
+            return fail(FSKMC_EINVAL, "reaction model needs 0 <= y <= 1, k_r >= 0, D >= 0");
+    }
+    return FSKMC_OK;
+}
+
 int sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const void* params,
                const fskmc_decomp* decomp, const fskmc_schedule* schedule, fskmc_key key, const fskmc_nested* nest,
                fskmc_sim** out)
@@ -1139,35 +1219,9 @@ int sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const vo
     S->ctx = ctx;
     S->model = model;
     S->lat = *lattice;
-    if (model == FSKMC_MODEL_FLIP) {
-        const fskmc_flip_params* p = (const fskmc_flip_params*)params;
-        double v[5] = {p->k_a, p->k_d, p->J, p->h, p->beta};
-        for (int i = 0; i < 5; ++i)
-            S->prm[i] = v[i];
-        if (!(p->k_a >= 0) || !(p->k_d >= 0) || !std::isfinite(p->J) || !std::isfinite(p->h) ||
-            !std::isfinite(p->beta) || !std::isfinite(p->k_a) || !std::isfinite(p->k_d)) {
-            delete S;
-            return fail(FSKMC_EINVAL, "spin-flip rates must be finite and k_a, k_d >= 0");
-        }
-    } else if (model == FSKMC_MODEL_KAWASAKI) {
-        const fskmc_kawasaki_params* p = (const fskmc_kawasaki_params*)params;
-        S->prm[0] = p->D;
-        S->prm[1] = p->J;
-        S->prm[2] = p->beta;
-        if (!(p->D >= 0) || !std::isfinite(p->D) || !std::isfinite(p->J) || !std::isfinite(p->beta)) {
-            delete S;
-            return fail(FSKMC_EINVAL, "spin exchange needs D >= 0 and finite D, J, beta");
-        }
-    } else {
-        const fskmc_zgb_params* p = (const fskmc_zgb_params*)params;
-        S->prm[0] = p->y;
-        S->prm[1] = p->k_r;
-        S->prm[2] = p->D;
-        if (!(p->y >= 0 && p->y <= 1) || !(p->k_r >= 0) || !(p->D >= 0) || !std::isfinite(p->k_r) ||
-            !std::isfinite(p->D)) {
-            delete S;
-            return fail(FSKMC_EINVAL, "reaction model needs 0 <= y <= 1, k_r >= 0, D >= 0");
-        }
+    if ((rc = parse_params(model, params, S->prm))) {
+        delete S;
+        return rc;
     }
     S->bx = decomp->bx;
     S->by = decomp->by;
@@ -1263,14 +1317,9 @@ int sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const vo
         return rc;
     }
     build_table(*S);
-    // every rate finite and small enough that a block's total stays finite
-    // (an infinite total would give zero waiting times and a window that
-    // never ends)
-    for (double r : S->table) {
-        if (!std::isfinite(r) || r < 0.0 || !std::isfinite(r * 4096.0)) {
-            delete S;
-            return fail(FSKMC_EINVAL, "rate %g is not finite or too large", r);
-        }
+    if ((rc = check_table(S->table.data(), (int)S->table.size()))) {
+        delete S;
+        return rc;
     }
     // persistent-sweep tables: next window of each colour, colour per block,
     // interacting blocks
@@ -1811,6 +1860,122 @@ int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t 
         }
         S->window = end;
     }
+    return FSKMC_OK;
+}
+
+int fskmc_advance_noalloc(int device, void* hip_stream, const fskmc_lattice* lattice, int model, const void* params,
+                          const fskmc_decomp* decomp, const fskmc_schedule* schedule, fskmc_key key,
+                          uint8_t* d_lattice, uint64_t w0, uint64_t n_windows, uint32_t* d_block_events,
+                          unsigned long long* d_events)
+{
+    // everything is checked before the first HIP call
+    if (!params || !decomp || !schedule || !d_lattice)
+        return fail(FSKMC_EINVAL, "NULL argument");
+    int rc = validate_lattice(lattice);
+    if (rc)
+        return rc;
+    if (model != FSKMC_MODEL_FLIP && model != FSKMC_MODEL_ZGB && model != FSKMC_MODEL_KAWASAKI)
+        return fail(FSKMC_EINVAL, "unknown model %d", model);
+    double prm[5];
+    if ((rc = parse_params(model, params, prm)))
+        return rc;
+    const int bx = decomp->bx, by = decomp->by, K = decomp->n_colours;
+    if (bx <= 0 || by <= 0 || lattice->Lx % bx || lattice->Ly % by)
+        return fail(FSKMC_EINVAL, "blocks %dx%d do not tile %dx%d", bx, by, lattice->Lx, lattice->Ly);
+    int P = 0, shape = 0;
+    if ((rc = kernel_shape(*lattice, model, bx, by, &P, &shape)))
+        return rc;
+    if (decomp->colour_map)
+        return fail(FSKMC_EINVAL, "the allocation-free advance takes the built-in colour maps only");
+    if (K != 2 && K != 4)
+        return fail(FSKMC_EINVAL, "built-in colour maps have 2 or 4 colours");
+    const int NBX = lattice->Lx / bx, NBY = lattice->Ly / by;
+    const int64_t nb64 = (int64_t)NBX * NBY;
+    if (nb64 > kNoallocMaxBlocks)
+        return fail(FSKMC_EINVAL, "%lld blocks exceed the %d of the allocation-free advance's static scratch",
+                    (long long)nb64, kNoallocMaxBlocks);
+    const int nb = (int)nb64;
+    // Independence of the built-in maps (Sec. 2.1), block by block: blocks are
+    // at least 8 sites on a side, so a block's closure reaches only the blocks
+    // next to it (spin flip: across a side; pair events: across a side or a
+    // corner), and no two of those may share its colour.
+    const bool pair = model != FSKMC_MODEL_FLIP;
+    auto colour = [&](int bi, int bj) { return K == 2 ? (bi + bj) % 2 : (bi % 2) + 2 * (bj % 2); };
+    int32_t count[4] = {0, 0, 0, 0};
+    for (int bj = 0; bj < NBY; ++bj)
+        for (int bi = 0; bi < NBX; ++bi) {
+            const int c = colour(bi, bj);
+            ++count[c];
+            for (int dj = -1; dj <= 1; ++dj)
+                for (int di = -1; di <= 1; ++di) {
+                    if ((di == 0 && dj == 0) || (!pair && di != 0 && dj != 0) || (lattice->dim == 1 && dj != 0))
+                        continue;
+                    const int ni = (bi + di + NBX) % NBX, nj = (bj + dj + NBY) % NBY;
+                    if ((ni != bi || nj != bj) && colour(ni, nj) == c)
+                        return fail(FSKMC_EDECOMP, "blocks of colour %d interact (blocks %d and %d)", c,
+                                    bj * NBX + bi, nj * NBX + ni);
+                }
+        }
+    int64_t steps = 0;
+    int per = 0;
+    if ((rc = scheme_steps(schedule->split, K, schedule->dt, schedule->T, &steps, &per)))
+        return rc;
+    const uint64_t total = (uint64_t)steps * (uint64_t)per;
+    if (w0 > total || n_windows > total - w0)
+        return fail(FSKMC_ESTATE, "windows [%llu, %llu) are past the schedule's %llu",
+                    (unsigned long long)w0, (unsigned long long)(w0 + n_windows), (unsigned long long)total);
+    double tab[243 * 14];
+    const int ntab = table_size(model, lattice->dim);
+    fill_table(model, lattice->dim, prm, tab);
+    if ((rc = check_table(tab, ntab)))
+        return rc;
+    int32_t off[4] = {0, 0, 0, 0};
+    for (int c = 1; c < 4; ++c)
+        off[c] = off[c - 1] + count[c - 1];
+
+    int prev = 0;
+    HIP_TRY(hipGetDevice(&prev));
+    uint8_t* base = nullptr;
+    hipError_t e = noalloc_scratch(device, &base);
+    if (e != hipSuccess)
+        return fail(FSKMC_EDEVICE, "scratch of device %d: %s", device, hipGetErrorString(e));
+    HIP_TRY(hipSetDevice(device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    double* d_tab = reinterpret_cast<double*>(base);
+    int32_t* d_blocks = reinterpret_cast<int32_t*>(base + kNoallocBlocksOff);
+    BlockCount* d_cnt = reinterpret_cast<BlockCount*>(base + kNoallocCountOff);
+    // the previous call's contents are overwritten; counters start at zero
+    e = launch_put_f64(d_tab, tab, ntab, st);
+    if (e == hipSuccess)
+        e = launch_builtin_blocks(d_blocks, NBX, NBY, K, off, st);
+    if (e == hipSuccess)
+        e = launch_fill_u64(reinterpret_cast<uint64_t*>(d_cnt), 2 * (int64_t)nb, 0ull, st);
+    for (uint64_t w = w0; e == hipSuccess && w < w0 + n_windows; ++w) {
+        int c = 0;
+        double d = 0.0;
+        scheme_window(schedule->split, K, schedule->dt, key, (int)(w % (uint64_t)per), (uint32_t)w, &c, &d);
+        SweepArgs a;
+        a.lat = d_lattice;
+        a.table = d_tab;
+        a.cnt = d_cnt;
+        a.blocks = d_blocks + off[c];
+        a.n_blocks = count[c];
+        a.Lx = lattice->Lx;
+        a.Ly = lattice->Ly;
+        a.NBX = NBX;
+        a.k0 = key.seed;
+        a.k1 = key.replica;
+        a.w = (uint32_t)w;
+        a.dur = d;
+        e = launch_sweep_single(kernel_model(model), P, shape, 2, a, st, LaunchTiming{});
+    }
+    if (e == hipSuccess && (d_block_events || d_events))
+        e = launch_noalloc_outputs(d_cnt, nb, d_block_events, d_events, st);
+    const hipError_t r = hipSetDevice(prev);
+    if (e != hipSuccess)
+        return fail(FSKMC_EDEVICE, "allocation-free advance: %s", hipGetErrorString(e));
+    if (r != hipSuccess)
+        return fail(FSKMC_EDEVICE, "hipSetDevice: %s", hipGetErrorString(r));
     return FSKMC_OK;
 }
 

@@ -206,4 +206,28 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_observe(const uint8_t* lat, int Lx, int Ly, int dim, const BlockCount* cnt, int n_blocks,
                           unsigned long long* out9, hipStream_t s);
 
+// Static scratch of the allocation-free advance: one file-scope device array
+// per GPU, laid out as the FP64 rate table (up to 243 x 14 entries), the
+// block ids grouped by colour and one counter record per block.
+constexpr int kNoallocMaxBlocks = 65536;
+constexpr size_t kNoallocTableBytes = 27648;  // >= 243 * 14 * 8, a multiple of 256
+constexpr size_t kNoallocBlocksOff = kNoallocTableBytes;
+constexpr size_t kNoallocCountOff = kNoallocBlocksOff + (size_t)kNoallocMaxBlocks * 4;
+constexpr size_t kNoallocBytes = kNoallocCountOff + (size_t)kNoallocMaxBlocks * sizeof(BlockCount);
+// Device address of the scratch array on `device`, looked up once per device
+// (with that device current) and kept; the caller's current device is
+// restored afterwards.
+hipError_t noalloc_scratch(int device, uint8_t** out);
+// n FP64 values written into dst by kernels whose arguments carry them (no
+// host-to-device copy).
+hipError_t launch_put_f64(double* dst, const double* host, int n, hipStream_t s);
+// Block ids grouped by colour for the built-in maps (2 colours (bi+bj)%2, 4
+// colours (bi%2)+2(bj%2)), each colour in ascending id order starting at
+// off[c].
+hipError_t launch_builtin_blocks(int32_t* out, int NBX, int NBY, int n_colours, const int32_t off[4], hipStream_t s);
+// W of every block into W (if not null) and the sum of the per-block event
+// counters into *events (if not null).
+hipError_t launch_noalloc_outputs(const BlockCount* cnt, int nb, uint32_t* W, unsigned long long* events,
+                                  hipStream_t s);
+
 }  // namespace fskmc

@@ -82,7 +82,7 @@ SYMBOLS = [
     "fskmc_ctx_set_kernel_timing", "fskmc_ctx_read_kernel_timing", "fskmc_ctx_set_persistent",
     "fskmc_ctx_set_resident", "fskmc_ctx_set_wait_limit", "fskmc_ctx_set_rebalance", "fskmc_sim_workload",
     "fskmc_workload_partition", "fskmc_sim_last_partition", "fskmc_sim_create_nested", "fskmc_ctx_set_nested",
-    "fskmc_ctx_set_batch_persistent", "fskmc_ctx_set_graphs",
+    "fskmc_ctx_set_batch_persistent", "fskmc_ctx_set_graphs", "fskmc_advance_noalloc",
 ]
 
 
@@ -130,6 +130,8 @@ def _load():
     L.fskmc_sim_footprint.argtypes = [P(fskmc_lattice), ctypes.c_int, P(fskmc_decomp), P(fskmc_schedule)]
     L.fskmc_sim_footprint.restype = ctypes.c_size_t
     L.fskmc_batch_advance.argtypes = [vp, P(vp), ctypes.c_int, ctypes.c_uint32]
+    L.fskmc_advance_noalloc.argtypes = [ctypes.c_int, vp, P(fskmc_lattice), ctypes.c_int, vp, P(fskmc_decomp),
+                                        P(fskmc_schedule), fskmc_key, vp, ctypes.c_uint64, ctypes.c_uint64, vp, vp]
     return L
 
 
@@ -374,6 +376,20 @@ def fskmc_sim_footprint(dim, Lx, Ly, model, bx, by, n_colours, dt, T, split):
 def fskmc_batch_advance(ctx, sims, windows):
     arr = (ctypes.c_void_p * len(sims))(*[s.value if isinstance(s, ctypes.c_void_p) else s for s in sims])
     _check(lib.fskmc_batch_advance(ctx, arr, len(sims), windows))
+
+
+def fskmc_advance_noalloc(device, hip_stream, dim, Lx, Ly, model, params, bx, by, n_colours, dt, T, split, seed,
+                          replica, d_lattice, w0, n_windows, d_block_events=None, d_events=None):
+    """Device pointers (ints) for the lattice and the optional outputs."""
+    lat = fskmc_lattice(dim, Lx, Ly)
+    p = _params(model, params)
+    dec, _ = _decomp(bx, by, n_colours, None)
+    sch = fskmc_schedule(dt, T, split)
+    _check(lib.fskmc_advance_noalloc(device, hip_stream, ctypes.byref(lat), model,
+                                     ctypes.cast(ctypes.byref(p), ctypes.c_void_p), ctypes.byref(dec),
+                                     ctypes.byref(sch), fskmc_key(seed, replica), ctypes.c_void_p(d_lattice), w0,
+                                     n_windows, ctypes.c_void_p(d_block_events) if d_block_events else None,
+                                     ctypes.c_void_p(d_events) if d_events else None))
 
 
 # --- convenience object ------------------------------------------------------

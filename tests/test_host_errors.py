@@ -51,3 +51,38 @@ def test_context_without_a_device(F):
         F.fskmc_ctx_create(0)
     assert ei.value.code == F.FSKMC_EDEVICE
 
+
+
+def test_noalloc_arguments_are_checked_before_any_hip_call(F):
+    """The allocation-free advance rejects every bad argument on the host
+    (these calls never reach the device, so they run without a GPU)."""
+    flip = (1.0, 1.0, 1.0, 0.0, 1.0)
+    fake = 0x1000  # never dereferenced: every case below fails its checks first
+
+    def call(Lx=64, Ly=64, model=F.FSKMC_MODEL_FLIP, params=flip, b=16, K=2, dt=0.1, T=1.0, split=0, w0=0, n=4,
+             lat=fake):
+        try:
+            F.fskmc_advance_noalloc(0, None, 1 if Ly == 1 else 2, Lx, Ly, model, params, b, b if Ly > 1 else 1, K,
+                                    dt, T, split, 0, 0, lat, w0, n)
+        except F.FskmcError as e:
+            return e.code
+        return F.FSKMC_OK
+
+    assert call(lat=0) == F.FSKMC_EINVAL                      # no lattice
+    assert call(Lx=8192, Ly=8192, b=16) == F.FSKMC_EINVAL     # 262144 blocks > the static scratch
+    assert call(b=12) == F.FSKMC_EINVAL                       # no kernel for 12x12 blocks
+    assert call(K=3) == F.FSKMC_EINVAL                        # built-in maps only
+    assert call(Lx=48, Ly=64) == F.FSKMC_EDECOMP              # 3 block columns: same colour across the wrap
+    assert call(model=F.FSKMC_MODEL_ZGB, params=(0.5, 1000.0, 10.0), b=32, K=2) == F.FSKMC_EDECOMP  # corners
+    assert call(T=1.05, dt=0.1) == F.FSKMC_EINVAL             # T / dt not an integer
+    assert call(w0=18, n=4) == F.FSKMC_ESTATE                 # 20 windows in the schedule
+    assert call(params=(1.0, -1.0, 1.0, 0.0, 1.0)) == F.FSKMC_EINVAL
+    L = F.lib
+    with_map = F.fskmc_decomp(16, 16, 2, (ctypes.c_int * 16)(*([0, 1, 0, 1, 1, 0, 1, 0] * 2)))
+    lat = F.fskmc_lattice(2, 64, 64)
+    p = F.fskmc_flip_params(*flip)
+    rc = L.fskmc_advance_noalloc(0, None, ctypes.byref(lat), F.FSKMC_MODEL_FLIP,
+                                 ctypes.cast(ctypes.byref(p), ctypes.c_void_p), ctypes.byref(with_map),
+                                 ctypes.byref(F.fskmc_schedule(0.1, 1.0, 0)), F.fskmc_key(0, 0),
+                                 ctypes.c_void_p(fake), 0, 1, None, None)
+    assert rc == F.FSKMC_EINVAL and b"built-in" in L.fskmc_last_error()
