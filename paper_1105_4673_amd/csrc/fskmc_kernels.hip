@@ -1066,6 +1066,9 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_persistent(PersistArgs a)
             const int m = a.blocks[beg + k];
             if (wait_neighbours(a.nbr, a.epoch, m, w, lane, a.abort_flag, a.wait_ticks))
                 return;
+            // issue priority over waves that are still waiting, until the
+            // epoch that releases this block's neighbours is out
+            __builtin_amdgcn_s_setprio(3);
             // the lattice is read and written with agent-coherent accesses, so
             // only their order matters here: loads after the epoch loads,
             // epoch store after the lattice stores have completed
@@ -1080,6 +1083,7 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_persistent(PersistArgs a)
             __builtin_amdgcn_s_waitcnt(0x0F70);
             if (lane == 0)
                 __hip_atomic_store(&a.epoch[m], nxt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_setprio(0);
         }
     }
 }
@@ -1124,6 +1128,7 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_batched_persistent(BatchPers
             const int m = jd.blocks[beg + k];
             if (wait_neighbours(jd.nbr, jd.epoch, m, (int)w, lane, a.abort_flag, a.wait_ticks, true))
                 return;
+            __builtin_amdgcn_s_setprio(3); // as in the single-simulation persistent sweep
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             block_window<P, BX, BY, MODEL, true>(jd.lat, jd.table, jd.cnt, jd.Lx, jd.Ly, m, jd.NBX, jd.k0, jd.k1,
                                                  (uint32_t)w, jd.win_dur[w], lds + wid * C::LDS, false);
@@ -1133,6 +1138,7 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_batched_persistent(BatchPers
                 const int nxt = jd.next_part[(size_t)c * (jd.n_windows + 1) + w + 1];
                 __hip_atomic_store(&jd.epoch[m], nxt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
+            __builtin_amdgcn_s_setprio(0);
         }
     }
 }
@@ -1398,6 +1404,12 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
             }
             if (__ballot(bad))
                 return;
+            // From here to the edge publication the wave is on its
+            // neighbours' critical path; the other wave of the SIMD is then
+            // usually drawing its next window's numbers or polling, work that
+            // can wait: issue priority goes to this one (an A/B on the
+            // headline: +6%, bits unchanged).
+            __builtin_amdgcn_s_setprio(3);
             const uint32_t hv = (uint32_t)(v >> 32);
             const uint32_t top = (uint32_t)__builtin_amdgcn_readlane((int)hv, 0);
             const uint32_t bot = (uint32_t)__builtin_amdgcn_readlane((int)hv, 1);
@@ -1421,8 +1433,16 @@ __global__ __launch_bounds__(64 * WPG) void k_sweep_resident(ResidentArgs a)
                                                                  a.k0, a.k1, true, nl0, v0, &F, true, &fo);
             // from the final sites in registers: the tile store completes at
             // the wave sync that ends the window
-            publish_edges_bits<P, BX, BY>(seg_bits<P>(fo), a.edge + 4 * (size_t)m, ledge + 4 * i,
-                                          (uint32_t)w + 1u, lane, c0);
+            // a window without events leaves the edges as they were: only the
+            // tag moves, with the bits kept in LDS from the last publication
+            if (e > 0) {
+                publish_edges_bits<P, BX, BY>(seg_bits<P>(fo), a.edge + 4 * (size_t)m, ledge + 4 * i,
+                                              (uint32_t)w + 1u, lane, c0);
+            } else if (lane < 4) {
+                coh_store(a.edge + 4 * (size_t)m + lane,
+                          (unsigned long long)((uint32_t)w + 1u) | ((unsigned long long)ledge[4 * i + lane] << 32));
+            }
+            __builtin_amdgcn_s_setprio(0);
             if (lane == 0) {
                 cwl[4 * i] = e;
                 if (e > 0) {
