@@ -19,6 +19,8 @@ CASES = [
     ("flip", 256, (1.0, 1.0, 1.0, 0.0, 1.0), 16, 2, 0.1, 10.0, 0, "bernoulli", (0, 40)),
     ("zgb", 128, (0.5, 1000.0, 10.0), 32, 4, 0.05, 2.0, 1, "empty", (0, 21)),
 ]
+# the largest lattice the static scratch takes: 65536 blocks of 16x16
+MAX_CASE = ("flip", 4096, (1.0, 1.0, 1.0, 0.0, 1.0), 16, 2, 0.1, 10.0, 2, "bernoulli", (0, 6))
 
 
 @pytest.fixture(scope="module")
@@ -58,5 +60,16 @@ def test_noalloc_equals_sim_advance_two_calls(F):
             assert lat.tobytes() == lat_s.tobytes(), case[0]
             assert np.array_equal(w, w_s), case[0]
             assert ev == ev_s and ev > 0, case[0]
+    finally:
+        F.fskmc_ctx_destroy(ctx)
+
+
+def test_noalloc_at_the_largest_block_count(F):
+    ctx = F.fskmc_ctx_create(0)
+    try:
+        F.fskmc_ctx_set_persistent(ctx, 0)
+        (lat, w, ev), (lat_s, w_s, ev_s) = _run(F, ctx, MAX_CASE)
+        assert w.size == 65536
+        assert lat.tobytes() == lat_s.tobytes() and np.array_equal(w, w_s) and ev == ev_s and ev > 0
     finally:
         F.fskmc_ctx_destroy(ctx)
