@@ -740,6 +740,9 @@ def main():
     ap.add_argument("--nested-cell", type=int, default=2)
     ap.add_argument("--only-headline", action="store_true",
                     help="the headline legs only (no per-window, C0, C1 grid, C2, balance, nested, batched, served)")
+    ap.add_argument("--counter-probes", type=int, default=0, metavar="MIB",
+                    help="only run plain torch kernels of known traffic over MIB MiB (HBM counter calibration): a "
+                         "write-only fill, a copy, a read-only sum, and sums over every 8th and every 16th 8-byte word")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -762,6 +765,26 @@ def main():
         log(f"cpu baseline: {cpu['value']:.3g} events/s on {cpu['cores']} cores ({cpu['per_core']:.3g} per core)")
 
     import torch
+    if args.counter_probes:
+        # each probe is its own dispatch (or two for the reductions); the
+        # profile summaries pair them with the bytes printed here
+        n = args.counter_probes << 20
+        x = torch.empty(n // 8, dtype=torch.int64, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        x.fill_(1)                       # writes n bytes
+        torch.cuda.synchronize()
+        y.copy_(x)                       # reads n, writes n
+        torch.cuda.synchronize()
+        s0 = x.sum()                     # reads n
+        torch.cuda.synchronize()
+        s8 = x[::8].sum()                # one 8-byte word per 64 bytes
+        torch.cuda.synchronize()
+        s16 = x[::16].sum()              # one 8-byte word per 128 bytes
+        torch.cuda.synchronize()
+        print(json.dumps({"probe_bytes": n, "sums": [int(s0), int(s8), int(s16)],
+                          "words_read": {"stride8": n // 64, "stride16": n // 128}}), flush=True)
+        return
     if args.copy_probe:
         n = args.copy_probe << 20
         src = torch.ones(n, dtype=torch.uint8, device="cuda")
