@@ -159,18 +159,25 @@ def nested_bytes(b, c, cells_per_launch, block_windows, launches):
     return launches * cells_per_launch * ((side + 2) ** 2 - 4 + side * side) + block_windows * 28
 
 
+def kernel_build_sha256():
+    """SHA-256 of the kernel source and the flags it is compiled with: the
+    key under which profiles/counters.json records a kernel's counters."""
+    from paper_1105_4673_amd import build as _b
+    with open(os.path.join(ROOT, "paper_1105_4673_amd", "csrc", "fskmc_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read() + " ".join(_b.FLAGS[:-4]).encode()).hexdigest()
+
+
 def _counters(symbol):
     """rocprofv3 counters recorded in profiles/counters.json for `symbol`
-    (only when recorded from the current kernel source), or None."""
+    (only when recorded from the current kernel source and flags), or None."""
     try:
         with open(os.path.join(ROOT, "profiles", "counters.json")) as f:
             rec = json.load(f)
-        with open(os.path.join(ROOT, "paper_1105_4673_amd", "csrc", "fskmc_kernels.hip"), "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        sha = kernel_build_sha256()
     except (OSError, ValueError):
         return None, None
     k = rec.get("kernels", {}).get(symbol)
-    if not k or k.get("kernel_source_sha256") != sha:
+    if not k or k.get("kernel_build_sha256") != sha:
         return None, rec
     return k, rec
 

@@ -11,9 +11,13 @@ SOURCES = [os.path.join(HERE, "csrc", "fskmc_kernels.hip"), os.path.join(HERE, "
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -ffp-contract=off: the decision path must round like the CPU statement of the
-# scheme (no fused multiply-add).  Packed FP32 instructions are disabled.
+# scheme (no fused multiply-add).  Packed FP32 instructions are disabled.  The
+# iterative ILP scheduler orders the kernels' dependent chains for latency
+# (the resident sweep's window: 1.7% shorter than the default scheduler's, the
+# same bits); it changes instruction order only.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
          "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-sched-strategy=iterative-ilp",
          "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
 
 
