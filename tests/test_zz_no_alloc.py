@@ -19,6 +19,11 @@ CASES = [
     ("flip", 256, (1.0, 1.0, 1.0, 0.0, 1.0), 16, 2, 0.1, 10.0, 0, "bernoulli", (0, 40)),
     ("zgb", 128, (0.5, 1000.0, 10.0), 32, 4, 0.05, 2.0, 1, "empty", (0, 21)),
 ]
+# other shapes and models: 1D rows of 64 sites, spin exchange on 4 colours
+MORE = [
+    ("flip1d", 4096, (1.0, 1.0, 0.5, 0.0, 1.0), 64, 2, 0.5, 5.0, 0, "bernoulli", (0, 12)),
+    ("kawasaki", 128, (4.0, 1.0, 1.0), 16, 4, 0.25, 3.0, 1, "bernoulli", (0, 14)),
+]
 # the largest lattice the static scratch takes: 65536 blocks of 16x16
 MAX_CASE = ("flip", 4096, (1.0, 1.0, 1.0, 0.0, 1.0), 16, 2, 0.1, 10.0, 2, "bernoulli", (0, 6))
 
@@ -31,18 +36,21 @@ def F():
 
 def _run(F, ctx, case):
     kind, L, prm, b, K, dt, T, split, start, (w0, n) = case
+    dim = 1 if kind.endswith("1d") else 2
+    kind = kind[:-2] if dim == 1 else kind
+    Ly, by = (1, 1) if dim == 1 else (L, b)
     model = F.MODELS[kind]
-    sim = F.Sim(ctx, kind, L, L, prm, b=b, n_colours=K, dt=dt, T=T, split=split, seed=0, replica=5)
+    sim = F.Sim(ctx, kind, L, Ly, prm, b=b, n_colours=K, dt=dt, T=T, split=split, seed=0, replica=5)
     sim.init(1 if start == "bernoulli" else 0, 0.5)
     lat0 = sim.lattice().copy()
-    nb = (L // b) ** 2
+    nb = (L // b) * (Ly // by)
     d_lat = torch.from_numpy(lat0).to("cuda")
     d_w = torch.full((nb,), -1, dtype=torch.int32, device="cuda")
     d_ev = torch.full((1,), -1, dtype=torch.int64, device="cuda")
     torch.cuda.synchronize()
-    print(f"noalloc: {kind} {L}x{L} b={b} windows [{w0}, {w0 + n})", flush=True)
-    F.fskmc_advance_noalloc(0, torch.cuda.current_stream().cuda_stream, 2, L, L, model, prm, b, b, K, dt, T, split,
-                            0, 5, d_lat.data_ptr(), w0, n, d_w.data_ptr(), d_ev.data_ptr())
+    print(f"noalloc: {kind} {L}x{Ly} b={b}x{by} windows [{w0}, {w0 + n})", flush=True)
+    F.fskmc_advance_noalloc(0, torch.cuda.current_stream().cuda_stream, dim, L, Ly, model, prm, b, by, K, dt, T,
+                            split, 0, 5, d_lat.data_ptr(), w0, n, d_w.data_ptr(), d_ev.data_ptr())
     torch.cuda.synchronize()
     got = (d_lat.cpu().numpy(), d_w.cpu().numpy().view(np.uint32), int(d_ev.cpu().item()))
     sim.advance(w0 + n)
@@ -60,6 +68,18 @@ def test_noalloc_equals_sim_advance_two_calls(F):
             assert lat.tobytes() == lat_s.tobytes(), case[0]
             assert np.array_equal(w, w_s), case[0]
             assert ev == ev_s and ev > 0, case[0]
+    finally:
+        F.fskmc_ctx_destroy(ctx)
+
+
+def test_noalloc_rows_and_spin_exchange(F):
+    ctx = F.fskmc_ctx_create(0)
+    try:
+        F.fskmc_ctx_set_persistent(ctx, 0)
+        for case in MORE:
+            (lat, w, ev), (lat_s, w_s, ev_s) = _run(F, ctx, case)
+            assert lat.tobytes() == lat_s.tobytes(), case[0]
+            assert np.array_equal(w, w_s) and ev == ev_s and ev > 0, case[0]
     finally:
         F.fskmc_ctx_destroy(ctx)
 
