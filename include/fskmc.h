@@ -370,7 +370,10 @@ int fskmc_ctx_read_kernel_timing(fskmc_ctx* ctx, double* total_ms, uint64_t* n_l
  * gives the same bits.
  *  - device, hip_stream: the GPU and the stream the work is enqueued on (NULL
  *    = that device's null stream).  Asynchronous: nothing is waited for, and
- *    the only HIP calls are kernel launches (no allocation, copy or memset).
+ *    the only work enqueued is kernel launches (no allocation, copy or
+ *    memset).  The calling thread's current device is switched to `device`
+ *    for the call and restored before it returns; the first call on a device
+ *    also looks up the array's device address (hipGetSymbolAddress).
  *  - lattice, model, params, schedule, key: as for fskmc_sim_create; decomp
  *    must use a built-in map (colour_map NULL, 2 or 4 colours).
  *  - d_lattice: device pointer, Lx*Ly bytes (site y*Lx + x), the state at
