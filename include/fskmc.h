@@ -368,8 +368,8 @@ int fskmc_ctx_read_kernel_timing(fskmc_ctx* ctx, double* total_ms, uint64_t* n_l
  * fskmc_sim_create would build from the same arguments, one launch per window
  * with the kernels of fskmc_sim_advance, on a lattice the caller owns, and
  * gives the same bits.
- *  - device, hip_stream: the GPU and the stream the work is enqueued on (NULL
- *    = that device's null stream).  Asynchronous: nothing is waited for, and
+ *  - device, hip_stream: the GPU and a stream of that GPU the work is enqueued
+ *    on (NULL = that device's null stream).  Asynchronous: nothing is waited for, and
  *    the only work enqueued is kernel launches (no allocation, copy or
  *    memset).  The calling thread's current device is switched to `device`
  *    for the call and restored before it returns; the first call on a device
