@@ -84,6 +84,44 @@ def test_noalloc_rows_and_spin_exchange(F):
         F.fskmc_ctx_destroy(ctx)
 
 
+def test_noalloc_chained_calls_and_empty_range(F):
+    """Windows [0, 17) then [17, 40) on the caller's lattice give the bits of
+    one call over [0, 40); a call over no windows leaves the lattice as it is
+    and reports no events."""
+    kind, L, prm, b, K, dt, T, split, _, _ = CASES[0]
+    model = F.MODELS[kind]
+    ctx = F.fskmc_ctx_create(0)
+    try:
+        sim = F.Sim(ctx, kind, L, L, prm, b=b, n_colours=K, dt=dt, T=T, split=split, seed=0, replica=5)
+        sim.init(1, 0.5)
+        lat0 = sim.lattice().copy()
+        sim.close()
+    finally:
+        F.fskmc_ctx_destroy(ctx)
+    nb = (L // b) ** 2
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def call(d_lat, w0, n):
+        d_w = torch.full((nb,), -1, dtype=torch.int32, device="cuda")
+        d_ev = torch.full((1,), -1, dtype=torch.int64, device="cuda")
+        F.fskmc_advance_noalloc(0, stream, 2, L, L, model, prm, b, b, K, dt, T, split, 0, 5, d_lat.data_ptr(), w0, n,
+                                d_w.data_ptr(), d_ev.data_ptr())
+        torch.cuda.synchronize()
+        return d_w.cpu().numpy().view(np.uint32), int(d_ev.cpu().item())
+
+    one = torch.from_numpy(lat0).to("cuda")
+    _, ev_one = call(one, 0, 40)
+    two = torch.from_numpy(lat0).to("cuda")
+    _, ev_a = call(two, 0, 17)
+    _, ev_b = call(two, 17, 23)
+    assert two.cpu().numpy().tobytes() == one.cpu().numpy().tobytes()
+    assert ev_a + ev_b == ev_one and ev_a > 0 and ev_b > 0
+    before = two.cpu().numpy().copy()
+    w, ev = call(two, 40, 0)
+    assert two.cpu().numpy().tobytes() == before.tobytes()
+    assert ev == 0 and not w.any()
+
+
 def test_noalloc_at_the_largest_block_count(F):
     ctx = F.fskmc_ctx_create(0)
     try:
