@@ -41,6 +41,13 @@
 namespace fskmc {
 
 // ---------------------------------------------------------------------------
+// a ^ b ^ c in one instruction (v_bitop3_b32, truth table 0x96: set where an
+// odd number of the three inputs is set); the compiler emits two XORs.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the two
 // multipliers 0xD2511F53, 0xCD9E8D57 with Weyl key increments 0x9E3779B9,
 // 0xBB67AE85.  Each round's two 32x32-bit products are taken whole (one
@@ -55,7 +62,8 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
             k1 += 0xBB67AE85u;
         }
         const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
-        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+        c = make_uint4(xor3((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1, xor3((uint32_t)(p0 >> 32), c.w, k1),
+                       (uint32_t)p0);
     }
     return c;
 }
