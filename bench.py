@@ -752,6 +752,9 @@ def main():
                          "write-only fill, a copy, a read-only sum, and sums over every 8th and every 16th 8-byte word")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
+    ap.add_argument("--maps-at-exit", default="", metavar="PATH",
+                    help="write /proc/self/maps to PATH at interpreter exit (to place the frames of a crash in a "
+                         "process-exit handler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -803,6 +806,12 @@ def main():
         return
 
     from paper_1105_4673_amd import fskmc as F
+    if args.maps_at_exit:
+        import atexit
+        import shutil
+        # registered after the binding's handler, so it runs first: the map
+        # still shows libfskmc where the process had it
+        atexit.register(shutil.copyfile, "/proc/self/maps", args.maps_at_exit)
 
     torch.cuda.init()
     ctx = F.fskmc_ctx_create(0, torch.cuda.current_stream().cuda_stream)
