@@ -696,6 +696,8 @@ def bench_served(F, ctx, rates, n_jobs, windows_per_step, budget_gib):
                   "offered_events_per_s": s["events"] / span if span > 0 else None,
                   "achieved_events_per_s": s["events_per_s"],
                   "sites_mean": sum(r.spec["Lx"] * r.spec["Ly"] for r in reqs) / n_jobs,
+                  "block_edges": {k: sorted({r.spec["b"] for r in reqs if r.spec["kind"] == k})
+                                  for k in sorted({r.spec["kind"] for r in reqs})},
                   "max_resident": srv.max_resident})
         log(f"served rate {rate}/s: {s['jobs']} jobs, {s['events']} events in {wall:.2f} s "
             f"(offered {s['offered_events_per_s']:.3g}, achieved {s['achieved_events_per_s']:.3g} events/s), "
