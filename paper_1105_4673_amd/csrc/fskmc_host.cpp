@@ -105,6 +105,13 @@ struct fskmc_ctx {
     unsigned long long* d_queue = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     std::vector<uint64_t> graph_key;
+    // batched advances with several kernel-variant groups: streams on which
+    // the groups' packed launches run side by side (created on first use),
+    // forked from and joined back into `stream` by events
+    int batch_streams = 4;
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> side_join;
+    hipEvent_t side_fork = nullptr;
 };
 
 struct fskmc_sim {
@@ -987,6 +994,14 @@ int fskmc_ctx_destroy(fskmc_ctx* c)
     (void)hipFree(c->d_queue);
     if (c->graph_exec)
         (void)hipGraphExecDestroy(c->graph_exec);
+    for (hipStream_t q : c->side) {
+        (void)hipStreamSynchronize(q);
+        (void)hipStreamDestroy(q);
+    }
+    for (hipEvent_t e : c->side_join)
+        (void)hipEventDestroy(e);
+    if (c->side_fork)
+        (void)hipEventDestroy(c->side_fork);
     (void)hipFree(c->d_jobs);
     (void)hipFree(c->d_items);
     (void)hipHostFree(c->h_stage);
@@ -997,6 +1012,16 @@ int fskmc_ctx_destroy(fskmc_ctx* c)
     if (c->own_stream && c->stream)
         (void)hipStreamDestroy(c->stream);
     delete c;
+    return FSKMC_OK;
+}
+
+int fskmc_ctx_set_batch_streams(fskmc_ctx* c, int streams)
+{
+    if (!c)
+        return fail(FSKMC_EINVAL, "ctx is NULL");
+    if (streams < 1 || streams > 4)
+        return fail(FSKMC_EINVAL, "streams must be 1..4");
+    c->batch_streams = streams;
     return FSKMC_OK;
 }
 
@@ -1648,6 +1673,38 @@ size_t fskmc_sim_footprint(const fskmc_lattice* lattice, int model, const fskmc_
     return footprint_of(N, model, nb, nw, K);
 }
 
+// At least n - 1 side streams (default priority) and their join events, plus
+// the fork event, created on the context's device.
+static int ensure_side_streams(fskmc_ctx* ctx, int n)
+{
+    if ((int)ctx->side.size() >= n - 1 && ctx->side_fork)
+        return FSKMC_OK;
+    int prev = 0;
+    HIP_TRY(hipGetDevice(&prev));
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipError_t e = hipSuccess;
+    if (!ctx->side_fork)
+        e = hipEventCreateWithFlags(&ctx->side_fork, hipEventDisableTiming);
+    while (e == hipSuccess && (int)ctx->side.size() < n - 1) {
+        hipStream_t q = nullptr;
+        hipEvent_t j = nullptr;
+        e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking);
+        if (e != hipSuccess)
+            break;
+        e = hipEventCreateWithFlags(&j, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            (void)hipStreamDestroy(q);
+            break;
+        }
+        ctx->side.push_back(q);
+        ctx->side_join.push_back(j);
+    }
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess)
+        return fail(FSKMC_EDEVICE, "side streams: %s", hipGetErrorString(e));
+    return FSKMC_OK;
+}
+
 int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t windows)
 {
     if (!ctx || (n > 0 && !sims) || n < 0)
@@ -1764,6 +1821,16 @@ int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t 
     HIP_TRY(hipEventRecord(ctx->stage_free, ctx->stream));
     const uint32_t K = ctx->batch_persist;
     hipStream_t st = ctx->stream;
+    // packed launches of different groups touch different sims: with several
+    // groups they run on streams of their own (group i on stream i mod ns),
+    // each group's windows in order on its stream, all joined back into the
+    // context's stream before the call's later work (not while kernel timing
+    // samples launches: the samples would overlap)
+    const int ns = (K == 0 && ctx->timing_stride == 0)
+                       ? std::min<int>((int)groups.size(), ctx->batch_streams) : 1;
+    if (ns > 1)
+        if (int rc = ensure_side_streams(ctx, ns))
+            return rc;
     // The launch sequence of this call: one packed launch per window and
     // group, or (K > 0) the epochs of every job, then per K windows and group
     // a cleared work counter and one persistent launch.  It reads the job
@@ -1772,15 +1839,31 @@ int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t 
     auto enqueue = [&]() -> hipError_t {
         hipError_t e = hipSuccess;
         if (K == 0) {
+            if (ns > 1) {
+                e = hipEventRecord(ctx->side_fork, st);
+                for (int q = 0; q + 1 < ns && e == hipSuccess; ++q)
+                    e = hipStreamWaitEvent(ctx->side[q], ctx->side_fork, 0);
+            }
             for (uint32_t step = 0; step < windows && e == hipSuccess; ++step)
-                for (auto& g : groups) {
+                for (size_t gi = 0; gi < groups.size(); ++gi) {
+                    const Group& g = groups[gi];
+                    const int q = (int)(gi % (size_t)ns);
                     const LaunchTiming tk = timing_begin(ctx);
                     e = launch_sweep_batched(g.model, g.P, g.shape, ctx->wpg, ctx->d_jobs + g.job_off,
-                                             ctx->d_items + g.item_off, g.items, step, st, tk);
+                                             ctx->d_items + g.item_off, g.items, step,
+                                             q == 0 ? st : ctx->side[q - 1], tk);
                     timing_end(ctx, tk);
                     if (e != hipSuccess)
                         break;
                 }
+            // the join is enqueued even after a failed launch, so a capture
+            // in progress still ends with every side stream merged back
+            for (int q = 0; q + 1 < ns; ++q) {
+                const hipError_t r = hipEventRecord(ctx->side_join[q], ctx->side[q]);
+                const hipError_t w = r == hipSuccess ? hipStreamWaitEvent(st, ctx->side_join[q], 0) : r;
+                if (e == hipSuccess)
+                    e = w;
+            }
             return e;
         }
         e = launch_epoch_init_batched(ctx->d_jobs, (int)n_jobs, st);
@@ -1816,7 +1899,7 @@ int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t 
         // everything the captured launches bake in, the wait limit included
         std::vector<uint64_t> key = {windows, K, (uint64_t)ctx->wpg, (uint64_t)(uintptr_t)ctx->d_jobs,
                                      (uint64_t)(uintptr_t)ctx->d_items, (uint64_t)(uintptr_t)st, n_jobs,
-                                     (uint64_t)ctx->wait_ticks};
+                                     (uint64_t)ctx->wait_ticks, (uint64_t)ns};
         for (auto& g : groups)
             key.insert(key.end(), {(uint64_t)g.model, (uint64_t)g.P, (uint64_t)g.shape, g.job_off, g.item_off,
                                    g.items, g.idx.size()});

@@ -82,7 +82,8 @@ SYMBOLS = [
     "fskmc_ctx_set_kernel_timing", "fskmc_ctx_read_kernel_timing", "fskmc_ctx_set_persistent",
     "fskmc_ctx_set_resident", "fskmc_ctx_set_wait_limit", "fskmc_ctx_set_rebalance", "fskmc_sim_workload",
     "fskmc_workload_partition", "fskmc_sim_last_partition", "fskmc_sim_create_nested", "fskmc_ctx_set_nested",
-    "fskmc_ctx_set_batch_persistent", "fskmc_ctx_set_graphs", "fskmc_advance_noalloc",
+    "fskmc_ctx_set_batch_persistent", "fskmc_ctx_set_graphs", "fskmc_ctx_set_batch_streams",
+    "fskmc_advance_noalloc",
 ]
 
 
@@ -114,6 +115,7 @@ def _load():
     L.fskmc_ctx_set_nested.argtypes = [vp, ctypes.c_int]
     L.fskmc_ctx_set_batch_persistent.argtypes = [vp, ctypes.c_int]
     L.fskmc_ctx_set_graphs.argtypes = [vp, ctypes.c_int]
+    L.fskmc_ctx_set_batch_streams.argtypes = [vp, ctypes.c_int]
     L.fskmc_sim_destroy.argtypes = [vp]
     L.fskmc_sim_attach_device_lattice.argtypes = [vp, vp, ctypes.c_size_t]
     L.fskmc_sim_init.argtypes = [vp, ctypes.c_int, ctypes.c_double]
@@ -291,6 +293,10 @@ def fskmc_ctx_set_nested(ctx, on):
 
 def fskmc_ctx_set_batch_persistent(ctx, windows):
     _check(lib.fskmc_ctx_set_batch_persistent(ctx, int(windows)))
+
+
+def fskmc_ctx_set_batch_streams(ctx, streams):
+    _check(lib.fskmc_ctx_set_batch_streams(ctx, int(streams)))
 
 
 def fskmc_ctx_set_graphs(ctx, on):

@@ -99,6 +99,25 @@ def test_batch_persistent_equals_alone(F, orc, ctx, K, graphs):
     assert got == want
 
 
+@pytest.mark.parametrize("streams", [1, 2, 4])
+@pytest.mark.parametrize("graphs", [1, 0], ids=["graph", "eager"])
+def test_batch_streams_equal_alone(F, orc, ctx, streams, graphs):
+    """The five kernel-variant groups of SPECS (spin flip on 16x16, 8x8 and
+    1D blocks, the reaction model on 32x32, spin exchange on 16x16) spread
+    over 1, 2 or 4 streams: every sim still gets the oracle's bits."""
+    F.fskmc_ctx_set_batch_persistent(ctx, 0)
+    F.fskmc_ctx_set_batch_streams(ctx, streams)
+    F.fskmc_ctx_set_graphs(ctx, graphs)
+    sims = _make(F, ctx, SPECS)
+    while any(s.windows()[1] < s.windows()[0] for s in sims):
+        F.fskmc_batch_advance(ctx, [s.handle for s in sims], 6)
+    F.fskmc_sync(ctx)
+    got = [_digest(s) for s in sims]
+    for s in sims:
+        s.close()
+    assert got == _oracle(orc, SPECS)
+
+
 def test_batch_full_and_small_launch_kernels(F, orc, ctx):
     """16 sites per lane in both launch kernels at once: the spin-flip group
     holds 2112 blocks per window (the full-launch kernel), the reaction group
@@ -176,6 +195,10 @@ def test_batch_knobs_invalid(F, ctx):
     with pytest.raises(F.FskmcError) as ei:
         F.fskmc_ctx_set_batch_persistent(ctx, -1)
     assert ei.value.code == F.FSKMC_EINVAL
+    for bad in (0, 5):
+        with pytest.raises(F.FskmcError) as ei:
+            F.fskmc_ctx_set_batch_streams(ctx, bad)
+        assert ei.value.code == F.FSKMC_EINVAL
 
 
 def test_autotune_windows_per_launch_picks_a_candidate(F, ctx):

@@ -24,7 +24,8 @@ def test_null_arguments_are_rejected(F):
     assert L.fskmc_sim_observe(None, None) == F.FSKMC_EINVAL
     assert L.fskmc_batch_advance(None, None, 1, 1) == F.FSKMC_EINVAL
     for setter in ("fskmc_ctx_set_persistent", "fskmc_ctx_set_resident", "fskmc_ctx_set_nested",
-                   "fskmc_ctx_set_batch_persistent", "fskmc_ctx_set_graphs", "fskmc_ctx_set_rebalance"):
+                   "fskmc_ctx_set_batch_persistent", "fskmc_ctx_set_graphs", "fskmc_ctx_set_rebalance",
+                   "fskmc_ctx_set_batch_streams"):
         assert getattr(L, setter)(None, 1) == F.FSKMC_EINVAL, setter
     assert L.fskmc_sim_destroy(None) == F.FSKMC_OK and L.fskmc_ctx_destroy(None) == F.FSKMC_OK
 
