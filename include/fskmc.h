@@ -252,9 +252,10 @@ size_t fskmc_sim_footprint(const fskmc_lattice* lattice, int model, const fskmc_
  * block) work items from a device counter in window order, each block
  * waiting only for the blocks it interacts with (Sec. 2.2 stage 2).  Sims
  * are grouped by kernel variant (model family, block shape); each group is
- * launched on its own, and with one packed launch per window the groups run
- * side by side on streams of their own (fskmc_ctx_set_batch_streams), joined
- * back into the context's stream before the call's later work.  The launch sequence is captured as a HIP graph and
+ * launched on its own, and with one packed launch per window launched
+ * directly (graphs off) the groups run side by side on streams of their own
+ * (fskmc_ctx_set_batch_streams), joined back into the context's stream before
+ * the call's later work.  The launch sequence is captured as a HIP graph and
  * replayed by later calls with the same layout (fskmc_ctx_set_graphs).
  * Each sim's result is bit-identical to advancing it alone.  FSKMC_EDEVICE
  * at the next synchronising call if a persistent wait timed out (the lattices
@@ -272,7 +273,8 @@ int fskmc_ctx_set_batch_persistent(fskmc_ctx* ctx, int windows);
  * context).  Groups advance different sims, so their launches may overlap;
  * each group's windows stay in order on its stream.  1 = every launch on the
  * context's stream.  Persistent batched launches (fskmc_ctx_set_batch_persistent
- * > 0) and launches sampled by kernel timing always use the context's stream.
+ * > 0), launches replayed from a captured graph (fskmc_ctx_set_graphs on) and
+ * launches sampled by kernel timing always use the context's stream.
  * FSKMC_EINVAL unless 1 <= streams <= 4. */
 int fskmc_ctx_set_batch_streams(fskmc_ctx* ctx, int streams);
 

@@ -1824,9 +1824,13 @@ int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t 
     // packed launches of different groups touch different sims: with several
     // groups they run on streams of their own (group i on stream i mod ns),
     // each group's windows in order on its stream, all joined back into the
-    // context's stream before the call's later work (not while kernel timing
-    // samples launches: the samples would overlap)
-    const int ns = (K == 0 && ctx->timing_stride == 0)
+    // context's stream before the call's later work.  Not while kernel timing
+    // samples launches (the samples would overlap), and not in a captured
+    // graph: a process took a host segmentation fault inside this call on its
+    // first capture across the side streams, with no cause found in this
+    // code, so graph capture keeps every launch on the context's stream.
+    const bool use_graph = ctx->graphs && ctx->timing_stride == 0;
+    const int ns = (K == 0 && ctx->timing_stride == 0 && !use_graph)
                        ? std::min<int>((int)groups.size(), ctx->batch_streams) : 1;
     if (ns > 1)
         if (int rc = ensure_side_streams(ctx, ns))
@@ -1895,7 +1899,7 @@ int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t 
         }
         return e;
     };
-    if (ctx->graphs && ctx->timing_stride == 0) {
+    if (use_graph) {
         // everything the captured launches bake in, the wait limit included
         std::vector<uint64_t> key = {windows, K, (uint64_t)ctx->wpg, (uint64_t)(uintptr_t)ctx->d_jobs,
                                      (uint64_t)(uintptr_t)ctx->d_items, (uint64_t)(uintptr_t)st, n_jobs,

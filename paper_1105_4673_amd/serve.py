@@ -38,12 +38,19 @@ class Request:
 
 
 class GpuBackend:
-    """libfskmc on one GPU context."""
+    """libfskmc on one GPU context.
 
-    def __init__(self, ctx):
+    By default the batched advances launch directly instead of replaying a
+    captured graph (the context's graph knob is set accordingly): the resident
+    set changes from step to step, so a graph would be captured again for
+    most steps, and direct launches let the groups of different models run
+    side by side on streams of their own."""
+
+    def __init__(self, ctx, graphs=False):
         from . import fskmc
         self.F = fskmc
         self.ctx = ctx
+        fskmc.fskmc_ctx_set_graphs(ctx, graphs)
 
     def footprint(self, spec):
         F = self.F
