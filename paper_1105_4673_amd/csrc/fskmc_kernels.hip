@@ -826,18 +826,24 @@ __device__ __forceinline__ uint32_t ssa_window(uint8_t* tile, double* tab, const
             // only leaves whose neighbourhood holds a changed site can change:
             // the columns around the event site and its partner; a lane holds
             // columns c0 .. c0+P-1 with c0 a multiple of P, so these are the
-            // leaves q = column mod P of every lane
-            int xa = lx, xb = lx;
-            if (pick > 0) {
-                const int d = (pick - 1) & 3;
-                xa = d == 1 ? lx - 1 : lx;
-                xb = d == 0 ? lx + 1 : lx;
+            // leaves q = column mod P of every lane.  With 4 or fewer leaves
+            // per lane those columns cover them all (a horizontal pair spans 4),
+            // and looking every leaf up without the per-leaf branches lets the
+            // lookups overlap.
+            uint32_t qmask = ~0u;
+            if constexpr (P > 4) {
+                int xa = lx, xb = lx;
+                if (pick > 0) {
+                    const int d = (pick - 1) & 3;
+                    xa = d == 1 ? lx - 1 : lx;
+                    xb = d == 0 ? lx + 1 : lx;
+                }
+                xa = xa > 0 ? xa - 1 : 0;
+                xb = xb < BX - 1 ? xb + 1 : BX - 1;
+                qmask = 0;
+                for (int x = xa; x <= xb; ++x)
+                    qmask |= 1u << (x % P);
             }
-            xa = xa > 0 ? xa - 1 : 0;
-            xb = xb < BX - 1 ? xb + 1 : BX - 1;
-            uint32_t qmask = 0;
-            for (int x = xa; x <= xb; ++x)
-                qmask |= 1u << (x % P);
             build_tree<P, BX, BY, MODEL, TS>(tile, tb, tab, T, qmask);
         }
         ++e;
