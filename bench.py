@@ -735,7 +735,7 @@ def main():
     ap.add_argument("--batched-jobs", type=int, default=512, help="0 skips the batched measurement")
     ap.add_argument("--served-jobs", type=int, default=256, help="requests per arrival rate; 0 skips serving")
     ap.add_argument("--served-rates", default="50,200,1000")
-    ap.add_argument("--served-windows-per-step", type=int, default=16)
+    ap.add_argument("--served-windows-per-step", type=int, default=64)
     ap.add_argument("--balance-windows", type=int, default=200,
                     help="windows of the half-filled 2048^2 rebalancing comparison; 0 skips it")
     ap.add_argument("--balance-chunk", type=int, default=20)
