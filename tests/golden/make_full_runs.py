@@ -61,6 +61,9 @@ CASES = {
                                                        10.0, "empty", 0, 1, 28),
     "reaction4096_b32_y0.5_D10_strang_dt0.05_r1_w280": ("zgb", 4096, 4096, _zgb(0.5, 10.0), 32, 4, orc.STRANG,
                                                         0.05, 10.0, "empty", 0, 1, 280),
+    # the timed 4096^2 reaction-lattice run (replica 0, whole run)
+    "reaction4096_b32_y0.5_D10_strang_dt0.05_T10_r0": ("zgb", 4096, 4096, _zgb(0.5, 10.0), 32, 4, orc.STRANG, 0.05,
+                                                       10.0, "empty", 0, 0, None),
     "reaction1024_b32_y0.5_D10_strang_dt0.05_T10_r1": ("zgb", 1024, 1024, _zgb(0.5, 10.0), 32, 4, orc.STRANG, 0.05,
                                                        10.0, "empty", 0, 1, None),
     # the 1024^2 job of the batched-kernel tests (whole run)
