@@ -1860,8 +1860,8 @@ int fskmc_batch_advance(fskmc_ctx* ctx, fskmc_sim* const* sims, int n, uint32_t 
                     if (e != hipSuccess)
                         break;
                 }
-            // the join is enqueued even after a failed launch, so a capture
-            // in progress still ends with every side stream merged back
+            // the join is enqueued even after a failed launch, so the
+            // context's stream never runs ahead of a side stream
             for (int q = 0; q + 1 < ns; ++q) {
                 const hipError_t r = hipEventRecord(ctx->side_join[q], ctx->side[q]);
                 const hipError_t w = r == hipSuccess ? hipStreamWaitEvent(st, ctx->side_join[q], 0) : r;
