@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/fskmc.h"
+#include "fskmc_decomp.h"
 #include "fskmc_internal.h"
 #include "fskmc_registry.h"
 
@@ -222,62 +223,15 @@ inline int kernel_model(int model)
     return model == FSKMC_MODEL_FLIP ? MODEL_FLIP : MODEL_ZGB;
 }
 
-// Neighbour of a site in direction d (0 +x, 1 -x, 2 +y, 3 -y), periodic.
-inline int64_t nbr(const fskmc_lattice& L, int64_t s, int d)
-{
-    int64_t x = s % L.Lx, y = s / L.Lx;
-    switch (d) {
-    case 0: x = (x + 1) % L.Lx; break;
-    case 1: x = (x + L.Lx - 1) % L.Lx; break;
-    case 2: y = (y + 1) % L.Ly; break;
-    default: y = (y + L.Ly - 1) % L.Ly; break;
-    }
-    return y * L.Lx + x;
-}
-
 // Independence of the blocks of each colour (Sec. 2.1, remark after eq.
-// gendecomp): no block may write a site that another block of the same colour
-// reads or writes.  Spin flip: W = C_m, R = C_m + N(C_m); pair events:
-// W = R = C_m + N(C_m).  One pass per colour with per-site owner marks.
+// gendecomp), checked on the blocks' boundaries (fskmc_decomp.h).
 int check_decomposition(const fskmc_sim& S)
 {
-    const fskmc_lattice& L = S.lat;
-    const int64_t N = n_sites(L);
-    const int nd = L.dim == 1 ? 2 : 4;
-    const bool pair = S.model != FSKMC_MODEL_FLIP;
-    std::vector<int32_t> ownW((size_t)N), ownR((size_t)N);
-    for (int c = 0; c < S.n_colours; ++c) {
-        std::fill(ownW.begin(), ownW.end(), -1);
-        std::fill(ownR.begin(), ownR.end(), -1);
-        for (int k = S.colour_off[c]; k < S.colour_off[c + 1]; ++k) {
-            const int m = S.blocks[k];
-            const int64_t x0 = (int64_t)(m % S.NBX) * S.bx, y0 = (int64_t)(m / S.NBX) * S.by;
-            auto mark = [&](int64_t s, bool write) -> bool {
-                if (write) {
-                    if ((ownW[s] != -1 && ownW[s] != m) || (ownR[s] != -1 && ownR[s] != m))
-                        return false;
-                    ownW[s] = m;
-                }
-                if (ownW[s] != -1 && ownW[s] != m)
-                    return false;
-                if (ownR[s] == -1)
-                    ownR[s] = m;
-                else if (ownR[s] != m)
-                    ownR[s] = -2; // several readers: any other writer conflicts
-                return true;
-            };
-            for (int64_t y = y0; y < y0 + S.by; ++y)
-                for (int64_t x = x0; x < x0 + S.bx; ++x) {
-                    const int64_t s = y * L.Lx + x;
-                    if (!mark(s, true))
-                        return fail(FSKMC_EDECOMP, "blocks of colour %d interact at site %lld", c, (long long)s);
-                    for (int d = 0; d < nd; ++d)
-                        if (!mark(nbr(L, s, d), pair))
-                            return fail(FSKMC_EDECOMP, "blocks of colour %d interact near site %lld", c,
-                                        (long long)s);
-                }
-        }
-    }
+    const DecompGeom G{S.lat.dim, S.lat.Lx, S.lat.Ly, S.bx, S.by, S.NBX};
+    int c = -1;
+    int64_t site = -1;
+    if (decomp_conflict(G, S.model != FSKMC_MODEL_FLIP, S.n_colours, S.blocks.data(), S.colour_off.data(), &c, &site))
+        return fail(FSKMC_EDECOMP, "blocks of colour %d interact at site %lld", c, (long long)site);
     return FSKMC_OK;
 }
 
