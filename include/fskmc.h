@@ -172,7 +172,10 @@ const char* fskmc_last_error(void);
  * spin flip writes C_m and reads C_m plus its neighbours; pair models read
  * and write C_m plus its neighbours), builds the window schedule and
  * allocates the device state.  params points at fskmc_flip_params,
- * fskmc_zgb_params or fskmc_kawasaki_params.  The lattice starts empty (all zeros). */
+ * fskmc_zgb_params or fskmc_kawasaki_params.  The lattice starts empty (all zeros).
+ * The uploads go through a stream of the context's own (created on first use,
+ * default priority): the call waits for them only, not for work already queued
+ * on the context's stream. */
 int fskmc_sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const void* params,
                      const fskmc_decomp* decomp, const fskmc_schedule* schedule, fskmc_key key,
                      fskmc_sim** out);

@@ -110,6 +110,9 @@ struct fskmc_ctx {
     // the groups' packed launches run side by side (created on first use),
     // forked from and joined back into `stream` by events
     int batch_streams = 4;
+    // uploads of new simulations (created on first use): creating one waits
+    // for its own uploads only, not for the work queued on `stream`
+    hipStream_t upload = nullptr;
     std::vector<hipStream_t> side;
     std::vector<hipEvent_t> side_join;
     hipEvent_t side_fork = nullptr;
@@ -952,6 +955,10 @@ int fskmc_ctx_destroy(fskmc_ctx* c)
         (void)hipStreamSynchronize(q);
         (void)hipStreamDestroy(q);
     }
+    if (c->upload) {
+        (void)hipStreamSynchronize(c->upload);
+        (void)hipStreamDestroy(c->upload);
+    }
     for (hipEvent_t e : c->side_join)
         (void)hipEventDestroy(e);
     if (c->side_fork)
@@ -1327,8 +1334,13 @@ int sim_create(fskmc_ctx* ctx, const fskmc_lattice* lattice, int model, const vo
         delete S;
         return rc;
     }
-    hipStream_t st = ctx->stream;
+    // the uploads and the zeroed lattice go through the context's upload
+    // stream and only that stream is waited for: work already queued on the
+    // context's stream (a running batch) keeps the GPU busy meanwhile
     hipError_t e = hipSuccess;
+    if (!ctx->upload)
+        e = hipStreamCreateWithFlags(&ctx->upload, hipStreamNonBlocking);
+    hipStream_t st = ctx->upload;
     if (e == hipSuccess)
         e = hipMemcpyAsync(S->d_bcol, bcol.data(), bcol.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && !S->cells.empty())
