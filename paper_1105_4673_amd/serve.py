@@ -89,11 +89,16 @@ class GpuBackend:
 class Server:
     """Admission by footprint and slots, continuous batching, retirement."""
 
-    def __init__(self, backend, hbm_budget, max_slots=1024, windows_per_step=4, clock=time.perf_counter):
+    def __init__(self, backend, hbm_budget, max_slots=1024, windows_per_step=4, clock=time.perf_counter,
+                 admit_per_step=None):
         self.b = backend
         self.budget = int(hbm_budget)
         self.max_slots = int(max_slots)
         self.k = int(windows_per_step)
+        # at most this many admissions per iteration (None: all that fit), so
+        # that a burst of arrivals is set up between launches of the jobs
+        # already resident instead of while the GPU waits for its first launch
+        self.admit_per_step = admit_per_step
         self.clock = clock
         self.queue = collections.deque()
         self.resident = []
@@ -132,7 +137,10 @@ class Server:
 
     def _admit(self, now):
         # first come, first served: the head of the queue waits for room
+        admitted = 0
         while self.queue and self.queue[0].arrival <= now and len(self.resident) < self.max_slots:
+            if self.admit_per_step is not None and admitted >= self.admit_per_step and self.resident:
+                break
             r = self.queue[0]
             if self.used + r.footprint > self.budget:
                 break
@@ -142,6 +150,7 @@ class Server:
             r.status = "running"
             self.used += r.footprint
             self.resident.append(r)
+            admitted += 1
 
     def _retire(self):
         keep = []

@@ -114,3 +114,19 @@ def test_percentiles_and_summary():
     s = summarize(done, wall=clk.t)
     assert s["jobs"] == 8 and s["events"] == 8 * 30
     assert s["p50_time_to_result_s"] <= s["p99_time_to_result_s"]
+
+
+def test_admissions_per_step_are_limited_in_arrival_order():
+    """A burst of five arrivals with at most two admissions per step: two jobs
+    join the first launch, two more the second, the last the third, in
+    arrival order; every job still finishes."""
+    clk = Clock()
+    be = FakeBackend(clk)
+    srv = Server(be, hbm_budget=100, max_slots=10, windows_per_step=1, clock=clk, admit_per_step=2)
+    reqs = [_req(i, 0.0, 4, 10) for i in range(5)]
+    done = srv.run(reqs, sleep=_sleep(clk))
+    assert be.batches[0] == ["j0", "j1"]
+    assert be.batches[1] == ["j0", "j1", "j2", "j3"]
+    assert be.batches[2] == ["j0", "j1", "j2", "j3", "j4"]
+    assert sorted(r.rid for r in done if r.status == "done") == [0, 1, 2, 3, 4]
+    assert [r.admitted for r in sorted(done, key=lambda q: q.rid)] == [0.0, 0.0, 1.0, 1.0, 2.0]
