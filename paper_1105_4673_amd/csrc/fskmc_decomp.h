@@ -8,10 +8,12 @@
 // neighbours all lie in its own block is marked by that block alone, and so
 // are its neighbours, unless they lie on the boundary, where they are marked
 // (as written) when the boundary itself is visited.  So each block marks its
-// boundary rows and columns (written) and their neighbours (read, or written
-// for pair events), which is the per-site check's set of marks restricted to
-// the sites two blocks can share; the verdict is the same.  Owner marks are
-// stamped with the colour instead of being cleared for every colour.
+// boundary rows and columns (written) and their neighbours in other blocks
+// (read, or written for pair events), which lie on those blocks' boundaries:
+// the per-site check's set of marks restricted to the sites two blocks can
+// share, so the verdict is the same.  Owner marks are kept per boundary
+// position only and stamped with the colour instead of being cleared for
+// every colour.
 #pragma once
 #include <cstdint>
 #include <memory>
@@ -26,40 +28,43 @@ struct DecompGeom {
     int bx, by, NBX;
 };
 
-// Neighbour of a site in direction d (0 +x, 1 -x, 2 +y, 3 -y), periodic.
-inline int64_t decomp_nbr(const DecompGeom& G, int64_t s, int d)
-{
-    int64_t x = s % G.Lx, y = s / G.Lx;
-    switch (d) {
-    case 0: x = (x + 1) % G.Lx; break;
-    case 1: x = (x + G.Lx - 1) % G.Lx; break;
-    case 2: y = (y + 1) % G.Ly; break;
-    default: y = (y + G.Ly - 1) % G.Ly; break;
-    }
-    return y * G.Lx + x;
-}
-
 // True when two blocks of one colour interact; then *bad_colour and *bad_site
 // name the colour and a site where they meet.  blocks[colour_off[c] ..
 // colour_off[c+1]) are the blocks of colour c.
 inline bool decomp_conflict(const DecompGeom& G, bool pair, int n_colours, const int32_t* blocks,
                             const int32_t* colour_off, int* bad_colour, int64_t* bad_site)
 {
-    const int64_t N = G.Lx * G.Ly;
-    const int nd = G.dim == 1 ? 2 : 4;
-    std::unique_ptr<int32_t[]> ownW(new int32_t[(size_t)N]), ownR(new int32_t[(size_t)N]);
-    std::vector<int16_t> stamp((size_t)N, (int16_t)-1); // colour whose marks ownW/ownR hold
+    const int64_t nb = (G.Lx / G.bx) * (G.Ly / G.by);
+    // boundary positions of a block, row by row: a row is visited whole when it
+    // is the block's top or bottom row (2D) or the block is at most 2 wide,
+    // else at its two ends; pos0[ly] = the first position of row ly
+    std::vector<int32_t> pos0((size_t)G.by + 1, 0);
+    std::vector<uint8_t> whole((size_t)G.by);
+    for (int ly = 0; ly < G.by; ++ly) {
+        whole[ly] = (G.dim == 2 && (ly == 0 || ly == G.by - 1)) || G.bx <= 2;
+        pos0[ly + 1] = pos0[ly] + (whole[ly] ? G.bx : 2);
+    }
+    const int64_t R = pos0[G.by];
+    const int64_t NBY = G.Ly / G.by;
+    // boundary position of site (lx, ly) of block m (the site is on the boundary)
+    auto pos = [&](int64_t m, int lx, int ly) -> size_t {
+        return (size_t)(m * R + pos0[ly] + (whole[ly] ? lx : (lx ? 1 : 0)));
+    };
+    // owner marks per boundary position, stamped with the colour they hold
+    const size_t M = (size_t)(nb * R);
+    std::unique_ptr<int32_t[]> ownW(new int32_t[M]), ownR(new int32_t[M]);
+    std::vector<int16_t> stamp(M, (int16_t)-1);
     for (int c = 0; c < n_colours; ++c) {
-        // mark site s for block m: conflict when another block wrote it, or
-        // when m writes it and another block read it
-        auto mark = [&](int64_t s, int32_t m, bool write) -> bool {
-            if (stamp[(size_t)s] != c) {
-                stamp[(size_t)s] = (int16_t)c;
-                ownW[(size_t)s] = -1;
-                ownR[(size_t)s] = -1;
+        // mark boundary position i for block m: conflict when another block
+        // wrote it, or when m writes it and another block read it
+        auto mark = [&](size_t i, int32_t m, bool write) -> bool {
+            if (stamp[i] != c) {
+                stamp[i] = (int16_t)c;
+                ownW[i] = -1;
+                ownR[i] = -1;
             }
-            int32_t& w = ownW[(size_t)s];
-            int32_t& r = ownR[(size_t)s];
+            int32_t& w = ownW[i];
+            int32_t& r = ownR[i];
             if (write) {
                 if ((w != -1 && w != m) || (r != -1 && r != m))
                     return false;
@@ -75,19 +80,32 @@ inline bool decomp_conflict(const DecompGeom& G, bool pair, int n_colours, const
         };
         for (int k = colour_off[c]; k < colour_off[c + 1]; ++k) {
             const int32_t m = blocks[k];
-            const int64_t x0 = (int64_t)(m % G.NBX) * G.bx, y0 = (int64_t)(m / G.NBX) * G.by;
-            for (int64_t y = y0; y < y0 + G.by; ++y) {
-                const bool edge_row = G.dim == 2 && (y == y0 || y == y0 + G.by - 1);
-                // the whole row on the block's top and bottom, else its two ends
-                const int64_t step = edge_row || G.bx <= 2 ? 1 : G.bx - 1;
-                for (int64_t x = x0; x < x0 + G.bx; x += step) {
-                    const int64_t s = y * G.Lx + x;
-                    bool ok = mark(s, m, true);
-                    for (int d = 0; d < nd && ok; ++d)
-                        ok = mark(decomp_nbr(G, s, d), m, pair);
+            const int64_t bi = m % G.NBX, bj = m / G.NBX;
+            // the blocks across each side (periodic; the block itself when it
+            // spans the lattice in that direction)
+            const int64_t mE = bj * G.NBX + (bi + 1) % G.NBX, mW = bj * G.NBX + (bi + G.NBX - 1) % G.NBX;
+            const int64_t mN = ((bj + 1) % NBY) * G.NBX + bi, mS = ((bj + NBY - 1) % NBY) * G.NBX + bi;
+            for (int ly = 0; ly < G.by; ++ly) {
+                const int step = whole[ly] ? 1 : G.bx - 1;
+                for (int lx = 0; lx < G.bx; lx += step) {
+                    bool ok = mark(pos(m, lx, ly), m, true);
+                    // a neighbour inside the block is the block's own site:
+                    // written by it when on its boundary, shared with no other
+                    // block otherwise; one across a side lies on the boundary
+                    // of the block there
+                    if (ok && lx + 1 == G.bx && mE != m)
+                        ok = mark(pos(mE, 0, ly), m, pair);
+                    if (ok && lx == 0 && mW != m)
+                        ok = mark(pos(mW, G.bx - 1, ly), m, pair);
+                    if (G.dim == 2) {
+                        if (ok && ly + 1 == G.by && mN != m)
+                            ok = mark(pos(mN, lx, 0), m, pair);
+                        if (ok && ly == 0 && mS != m)
+                            ok = mark(pos(mS, lx, G.by - 1), m, pair);
+                    }
                     if (!ok) {
                         *bad_colour = c;
-                        *bad_site = s;
+                        *bad_site = (bj * G.by + ly) * G.Lx + bi * G.bx + lx;
                         return true;
                     }
                 }

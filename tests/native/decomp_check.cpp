@@ -13,6 +13,21 @@
 
 using fskmc::DecompGeom;
 
+// neighbour of a site in direction d (0 +x, 1 -x, 2 +y, 3 -y), periodic
+static int64_t site_nbr(const DecompGeom& G, int64_t s, int d)
+{
+    int64_t x = s % G.Lx, y = s / G.Lx;
+    if (d == 0)
+        x = (x + 1) % G.Lx;
+    else if (d == 1)
+        x = (x + G.Lx - 1) % G.Lx;
+    else if (d == 2)
+        y = (y + 1) % G.Ly;
+    else
+        y = (y + G.Ly - 1) % G.Ly;
+    return y * G.Lx + x;
+}
+
 // every site of every block of a colour: own sites written, neighbours read
 // (written for pair events); a conflict is a site written by one block and
 // touched by another
@@ -33,7 +48,7 @@ static bool conflict_all_sites(const DecompGeom& G, bool pair, int K, const std:
                     writers[s].push_back(m);
                     touchers[s].push_back(m);
                     for (int d = 0; d < nd; ++d) {
-                        const int64_t t = fskmc::decomp_nbr(G, s, d);
+                        const int64_t t = site_nbr(G, s, d);
                         touchers[t].push_back(m);
                         if (pair)
                             writers[t].push_back(m);
