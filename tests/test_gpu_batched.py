@@ -103,8 +103,10 @@ def test_batch_persistent_equals_alone(F, orc, ctx, K, graphs):
 @pytest.mark.parametrize("graphs", [1, 0], ids=["graph", "eager"])
 def test_batch_streams_equal_alone(F, orc, ctx, streams, graphs):
     """The five kernel-variant groups of SPECS (spin flip on 16x16, 8x8 and
-    1D blocks, the reaction model on 32x32, spin exchange on 16x16) spread
-    over 1, 2 or 4 streams: every sim still gets the oracle's bits."""
+    1D blocks, the reaction model on 32x32, spin exchange on 16x16) with 1, 2
+    or 4 streams: launched directly the groups spread over that many streams,
+    replayed from a graph they stay on the context's stream; either way every
+    sim gets the oracle's bits."""
     F.fskmc_ctx_set_batch_persistent(ctx, 0)
     F.fskmc_ctx_set_batch_streams(ctx, streams)
     F.fskmc_ctx_set_graphs(ctx, graphs)
